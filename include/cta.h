@@ -1,0 +1,267 @@
+/*
+ * cta.h -- C ABI of the MI355X (gfx950) tensor-equation solver.
+ *
+ * The library solves the regularised tensor equation
+ *
+ *     N(X) = X x_1 G_1 ... x_N G_N + lambda * sum_k X x_k R_k = B,
+ *     G_k = A_k^T A_k,  R_k = D_k^T D_k,  B = Y x_1 A_1^T ... x_N A_N^T,
+ *
+ * built from the paper's separable transformation (Sec. 2.1, eq.
+ * separable_transf), its tensor equation (Sec. 3, eq. TensorEq), the
+ * normal-equation pattern A^T A of tensor transposition (App. A.7) and the
+ * Kronecker-sum regulariser of the discrete Poisson equation (Sec. 4.1), with
+ * the tensor conjugate gradients of Fig. Tensor_CG.  The operator is never
+ * formed: it is applied as a chain of mode products (Sec. 4.1: sequential
+ * separable transformations along individual dimensions).
+ *
+ * Conventions for every call:
+ *  - Tensors are dense, row-major (C order): mode 1 varies slowest, mode N is
+ *    contiguous.  Matrices are row-major.  A mode product X x_k M contracts
+ *    the column index of M with index k of X and puts the row index of M at
+ *    position k (ordered spaces, Sec. 2.1).
+ *  - Pointers named host_* are host memory; every other data pointer is
+ *    device memory on the current HIP device.  Tensor pointers must be
+ *    aligned to 16 bytes.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on that stream.  Calls marked "asynchronous" return
+ *    after enqueueing; the caller synchronises before reading results.
+ *  - The caller allocates and owns every tensor it passes.  Handles own only
+ *    their factor copies and workspace and release them in *_destroy.
+ *  - Errors are reported by status code only; no call aborts or throws.
+ *    cta_last_error() returns a thread-local message for the last non-OK
+ *    status returned on the calling thread.
+ *  - One handle is used from one host thread and one stream at a time.
+ */
+#ifndef CTA_H
+#define CTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CTA_OK = 0,
+    CTA_NOT_CONVERGED = 1,   /* result written, tolerance not reached */
+    CTA_ERR_ARG = -1,        /* null pointer, bad count, bad option value */
+    CTA_ERR_SHAPE = -2,      /* extents inconsistent or above the limits */
+    CTA_ERR_DTYPE = -3,      /* dtype combination not supported */
+    CTA_ERR_HIP = -4,        /* a HIP runtime call failed */
+    CTA_ERR_NOMEM = -5,      /* device allocation failed */
+    CTA_ERR_BREAKDOWN = -6,  /* CG breakdown: <p, N p> <= 0 or non-finite */
+    CTA_ERR_UNSUPPORTED = -7 /* valid request outside what this build handles */
+} cta_status;
+
+typedef enum { CTA_F64 = 0, CTA_F32 = 1, CTA_BF16 = 2 } cta_dtype;
+
+/* Arithmetic of the operator chain inside a solve or an operator apply.
+ *  CTA_PREC_F64        FP64 tensors, FP64 MFMA, FP64 dots.
+ *  CTA_PREC_F32        FP32 tensors, FP32 MFMA, FP64 dots.
+ *  CTA_PREC_BF16       FP32 vectors; chain inputs and intermediates rounded to
+ *                      BF16 (nearest-even), BF16 MFMA with FP32 accumulation;
+ *                      regulariser in FP32; FP64 dots.
+ *  CTA_PREC_BF16_REFINE  (solves only) FP64 outer iterative refinement with an
+ *                      FP64 residual recomputation, inner CG in CTA_PREC_BF16. */
+typedef enum {
+    CTA_PREC_F64 = 0,
+    CTA_PREC_F32 = 1,
+    CTA_PREC_BF16 = 2,
+    CTA_PREC_BF16_REFINE = 3
+} cta_precision;
+
+/* Largest extent of any mode (rows or columns of any factor). */
+#define CTA_MAX_EXTENT 256
+/* Largest tensor order. */
+#define CTA_MAX_ORDER 8
+
+const char* cta_last_error(void);
+/* Library version string, e.g. "cta 0.1.0 gfx950". */
+const char* cta_version(void);
+
+/* ------------------------------------------------------------------------
+ * General multi-mode product (Sec. 2.1, eq. separable_transf; Sec. 2, eq.
+ * first_product restricted to separable operators).
+ *
+ * Y = X x_{k in mode_mask} op_k(M_k), op_k(M) = M, or M^T when bit k of
+ * trans_mask is set.  M_k is stored row-major with m_rows[k] x m_cols[k]
+ * entries; op_k(M_k) must have as many columns as X has extent on mode k, and
+ * its row count is the extent of Y on mode k.  Modes outside mode_mask are
+ * copied unchanged.  The evaluation order is chosen by the library to
+ * minimise flops (products on distinct modes commute, Sec. 2.1).  Arrays
+ * x_dims, M, m_rows, m_cols have `order` entries (entries of modes outside
+ * mode_mask are ignored).  Inputs and outputs may be F64, F32 or BF16 in any
+ * combination; `compute` fixes the MFMA arithmetic and the storage type of
+ * intermediates.  Workspace: device memory of at least
+ * cta_ttm_workspace_bytes(...) bytes, owned by the caller, not retained.
+ * Asynchronous.  X and Y must not overlap.
+ * ---------------------------------------------------------------------- */
+size_t cta_ttm_workspace_bytes(int order, const int64_t* x_dims, uint32_t mode_mask,
+                               uint32_t trans_mask, const int64_t* m_rows,
+                               const int64_t* m_cols, cta_dtype compute);
+cta_status cta_ttm(int order, const int64_t* x_dims, const void* X, cta_dtype x_dtype,
+                   uint32_t mode_mask, uint32_t trans_mask, const void* const* M,
+                   const int64_t* m_rows, const int64_t* m_cols, cta_dtype m_dtype,
+                   cta_dtype compute, void* Y, cta_dtype y_dtype, void* workspace,
+                   size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Operator handle: the per-mode factors of one tensor equation.
+ *
+ * order N in [2, CTA_MAX_ORDER]; n[k] unknown extents; m[k] sample extents;
+ * host_A[k]: A_k, row-major m[k] x n[k], FP64 host memory.  host_D may be
+ * NULL (no regulariser); otherwise host_D[k] is D_k, row-major p[k] x n[k]
+ * (p[k] may be 0 for "no regulariser on mode k").  lambda >= 0 is expected
+ * (a negative value is accepted; CG then reports CTA_ERR_BREAKDOWN if the
+ * operator is not positive definite).  The handle computes G_k and R_k in
+ * FP64 on the host (App. A.7), stores them on the device in FP64, FP32 and
+ * BF16, and allocates its solver workspace (about 12 tensors of n's size).
+ * Synchronous with respect to `stream`.
+ * ---------------------------------------------------------------------- */
+typedef struct cta_op_s* cta_op;
+
+cta_status cta_op_create(cta_op* out, int order, const int64_t* n, const int64_t* m,
+                         const double* const* host_A, const double* const* host_D,
+                         const int64_t* p, double lambda, void* stream);
+cta_status cta_op_destroy(cta_op op);
+/* Device bytes owned by the handle. */
+size_t cta_op_device_bytes(cta_op op);
+
+/* Y = X x_1 A_1 ... x_N A_N (forward model; X has extents n, Y extents m).
+ * Asynchronous.  Uses the handle's workspace (not reentrant per handle). */
+cta_status cta_forward(cta_op op, const void* X, cta_dtype x_dtype, void* Y,
+                       cta_dtype y_dtype, cta_precision chain, void* stream);
+
+/* B = Y x_1 A_1^T ... x_N A_N^T (App. A.7).  Y has extents m, B extents n.
+ * The chain runs in `chain` precision (CTA_PREC_F64 or CTA_PREC_F32).
+ * Asynchronous. */
+cta_status cta_rhs(cta_op op, const void* Y, cta_dtype y_dtype, void* B, cta_dtype b_dtype,
+                   cta_precision chain, void* stream);
+
+/* Q = N(P) with P, Q of extents n and dtype `dtype` (F64 for CTA_PREC_F64,
+ * F32 for CTA_PREC_F32 and CTA_PREC_BF16).  If `dot` is not NULL the FP64
+ * inner product <P, Q> (App. A.6) is written to the device double *dot.
+ * Asynchronous.  P and Q must not overlap. */
+cta_status cta_apply_normal_op(cta_op op, const void* P, void* Q, cta_dtype dtype,
+                               cta_precision chain, double* dot, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Conjugate-gradient solve (Fig. Tensor_CG) of N(X) = B.
+ *
+ * Stopping test: ||r||_2 <= rtol * ||B||_2 on the recursive residual (the
+ * printed "until rho > threshold" is read as rho <= threshold, as in the
+ * Jacobi solver of Fig. Tensor_Jacobi); on exit the true residual is
+ * recomputed in FP64.
+ * Precision / dtype of B and X:
+ *   CTA_PREC_F64          B, X F64
+ *   CTA_PREC_F32          B, X F32
+ *   CTA_PREC_BF16         B, X F32  (inner arithmetic only; rarely reaches 1e-8)
+ *   CTA_PREC_BF16_REFINE  B, X F64  (outer FP64 refinement to rtol, inner CG
+ *                                    in CTA_PREC_BF16 to inner_rtol)
+ * X is read as the starting tensor when x0_given != 0, else overwritten.
+ * With fallback_zero != 0 a starting tensor whose residual is not smaller than
+ * ||B|| is replaced by zero.  The call synchronises `stream` and fills
+ * *host_info.  Returns CTA_OK, CTA_NOT_CONVERGED (max_iter or max_refine hit;
+ * the last X is written) or an error.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    cta_precision precision;
+    double rtol;        /* relative residual target, e.g. 1e-8 */
+    int max_iter;       /* CG iterations (for refinement: per inner solve) */
+    int x0_given;       /* 1: X holds the starting tensor */
+    int fallback_zero;  /* 1: use zero if the start is worse than zero */
+    double inner_rtol;  /* refinement: inner relative tolerance (e.g. 1e-2) */
+    int max_refine;     /* refinement: outer steps */
+    int check_every;    /* host reads the convergence flag every this many iterations */
+} cta_cg_opts;
+
+typedef struct {
+    int status;               /* cta_status of this solve */
+    int iters;                /* total CG iterations (all inner solves) */
+    int refine_steps;         /* outer refinement steps (0 without refinement) */
+    double rel_res_recursive; /* ||r_rec|| / ||B|| at exit */
+    double rel_res_true;      /* ||B - N(X)|| / ||B|| recomputed in FP64 */
+    double seconds;           /* wall time of the solve (host clock) */
+} cta_cg_info;
+
+/* Defaults: F32, rtol 1e-6, max_iter 10000, no start, inner_rtol 1e-2,
+ * max_refine 30, check_every 16. */
+void cta_cg_opts_default(cta_cg_opts* opts);
+
+cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype dtype,
+                        const cta_cg_opts* opts, cta_cg_info* host_info, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched solve: `count` independent problems of order 3 in one persistent
+ * launch.  ops[i] is the handle of problem i (each with its own shapes and
+ * lambda), B[i] and X[i] its device tensors (dtype F32, CTA_PREC_F32 only).
+ * Work is ordered largest problem first; each problem is solved by a team of
+ * workgroups that synchronise through device-memory barriers; the kernel's
+ * tile shapes come from the autotuner cache (cta_tune_batched) when present.
+ * Synchronises `stream` and fills host_infos[count].
+ * ---------------------------------------------------------------------- */
+cta_status cta_solve_batched(int count, const cta_op* ops, const void* const* B,
+                             void* const* X, cta_dtype dtype, const cta_cg_opts* opts,
+                             cta_cg_info* host_infos, void* stream);
+
+/* Autotuner: times every candidate tile configuration of the batched solver
+ * for each distinct problem shape among ops[0..count) on `stream`, validates
+ * each candidate's operator output against the reference configuration,
+ * and stores the fastest median per shape in the process-wide cache, which
+ * cta_solve_batched reads.  When `cache_path` is not NULL the cache is also
+ * written there as JSON (and read back by cta_tune_load). */
+cta_status cta_tune_batched(int count, const cta_op* ops, int reps, const char* cache_path,
+                            void* stream);
+cta_status cta_tune_load(const char* cache_path);
+/* Copy a JSON description of the current cache into host_buf (NUL
+ * terminated, truncated to bytes); returns the full length via *needed. */
+cta_status cta_tune_dump(char* host_buf, size_t bytes, size_t* needed);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start: a separable network (per-mode 1-D convolutions, the
+ * convolution row of Table 1) mapping B to a starting tensor X0.
+ *
+ * Architecture (order 4 tensors only): input B / ||B||; pointwise lift
+ * 1 -> C channels; `blocks` residual blocks, each four convolutions of width
+ * `width` along modes 1..4 (zero padding, C -> C channels, bias) with ReLU
+ * after the first three; pointwise projection C -> 1; output times ||B||.
+ * FP32 master weights and Adam state; BF16 copies of weights and
+ * activations in the convolutions with FP32 accumulation on MFMA.
+ * C must be 32 and width 5 in this build.
+ * ---------------------------------------------------------------------- */
+typedef struct cta_ws_s* cta_ws;
+
+cta_status cta_ws_create(cta_ws* out, int order, const int64_t* n, int channels, int width,
+                         int blocks, uint64_t seed, void* stream);
+cta_status cta_ws_destroy(cta_ws w);
+/* Number of FP32 parameters. */
+int64_t cta_ws_num_params(cta_ws w);
+/* X0 = f(B) for one F32 tensor B (extents n).  training != 0 keeps the
+ * activations for cta_ws_backward.  Asynchronous. */
+cta_status cta_ws_forward(cta_ws w, const void* B, void* X0, int training, void* stream);
+/* Given dL/dX0 (F32, extents n) of the last training forward, accumulate the
+ * parameter gradient.  Asynchronous. */
+cta_status cta_ws_backward(cta_ws w, const void* dX0, void* stream);
+/* Mean-squared-error loss L = mean((X0 - T)^2) of the last forward output X0
+ * against target T (F32): writes dL/dX0 to dX0 and L to the device double
+ * *loss (may be NULL).  Asynchronous. */
+cta_status cta_ws_mse(cta_ws w, const void* X0, const void* T, void* dX0, double* loss,
+                      void* stream);
+/* Zero the accumulated gradient.  Asynchronous. */
+cta_status cta_ws_zero_grad(cta_ws w, void* stream);
+/* One Adam step on the FP32 master weights with the accumulated gradient
+ * (step counter kept in the handle), then refresh the BF16 copies.
+ * Asynchronous. */
+cta_status cta_ws_adam_step(cta_ws w, float lr, float beta1, float beta2, float eps,
+                            void* stream);
+/* Copy the FP32 master parameters (set == 0) or the accumulated FP32
+ * gradient (set == 2) to host_buf, or load parameters from it (set == 1).
+ * `bytes` must equal 4 * cta_ws_num_params.  Synchronous. */
+cta_status cta_ws_params(cta_ws w, void* host_buf, size_t bytes, int set, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTA_H */

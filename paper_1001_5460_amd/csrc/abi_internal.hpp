@@ -1,0 +1,46 @@
+// Internal definitions shared by the host-side translation units of libcta.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/cta.h"
+#include "launch.hpp"
+
+// Operator handle: per-mode factors on the device and the solver workspace.
+struct cta_op_s {
+    int order = 0;       // internal order (order 2 is lifted to 3)
+    int user_order = 0;
+    int lift = 0;        // leading unit modes added
+    int64_t n[CTA_MAX_ORDER] = {0};
+    int64_t m[CTA_MAX_ORDER] = {0};
+    double lam = 0.0;
+    int64_t N = 0;       // unknowns
+    int64_t Msamp = 0;   // samples
+    int64_t big = 0;     // prod_k max(n_k, m_k): bound of chain intermediates
+    cta::Mat G[3][CTA_MAX_ORDER];   // G_k = A_k^T A_k per compute dtype
+    cta::Mat A[2][CTA_MAX_ORDER];   // A_k   (F64, F32)
+    cta::Mat At[2][CTA_MAX_ORDER];  // A_k^T (F64, F32)
+    void* rband[2][CTA_MAX_ORDER] = {{nullptr}};  // R_k bands (F64, F32)
+    void* T1 = nullptr;  // chain intermediates (N x 8 bytes each)
+    void* T2 = nullptr;
+    void* vx = nullptr;  // CG vectors (N x 8 bytes each)
+    void* vr = nullptr;
+    void* vp = nullptr;
+    void* vq = nullptr;
+    void* vaux = nullptr;
+    void* rw0 = nullptr;  // forward / rhs work buffers (big x 8 bytes each, lazy)
+    void* rw1 = nullptr;
+    cta::CgScalars* scal = nullptr;
+    cta::CgScalars* hscal = nullptr;  // pinned host mirror
+    double* partials = nullptr;
+    std::vector<void*> allocs;
+    size_t dev_bytes = 0;
+};
+
+namespace cta {
+cta_status fail(cta_status st, const char* fmt, ...);
+cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post, double* dot_out,
+                        bool fuse_update, hipStream_t s);
+}  // namespace cta

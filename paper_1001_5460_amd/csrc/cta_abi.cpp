@@ -1,0 +1,660 @@
+// Host side of the C ABI: argument validation, factor setup (App. A.7),
+// mode-order planning (Sec. 2.1), the CG driver (Fig. Tensor_CG) and the
+// FP64 iterative refinement around a BF16 inner solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/cta.h"
+#include "abi_internal.hpp"
+#include "launch.hpp"
+
+using namespace cta;
+
+// ---------------------------------------------------------------------------
+// errors
+static thread_local std::string g_err;
+
+namespace cta {
+cta_status fail(cta_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+}  // namespace cta
+
+extern "C" const char* cta_last_error(void) { return g_err.c_str(); }
+extern "C" const char* cta_version(void) { return "cta 0.1.0 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// host helpers
+namespace cta {
+
+static uint16_t host_bf16(double x) {
+    // double -> float (nearest) -> bf16 (nearest even), as the device does
+    const float f = (float)x;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Upload a rows x cols row-major FP64 host matrix (optionally transposed) as a
+// zero-padded device copy in dtype dt.
+cta_status upload_mat(const double* host, int rows, int cols, bool trans, int dt, Mat* out,
+                      std::vector<void*>& allocs, size_t& bytes_acc) {
+    const int R = trans ? cols : rows, C = trans ? rows : cols;
+    const int rs = (int)round_up(R, 64), ld = (int)round_up(C, 32);
+    const size_t es = dt_size(dt);
+    std::vector<unsigned char> buf((size_t)rs * ld * es, 0);
+    for (int i = 0; i < R; ++i)
+        for (int j = 0; j < C; ++j) {
+            const double v = trans ? host[(size_t)j * cols + i] : host[(size_t)i * cols + j];
+            unsigned char* dst = buf.data() + ((size_t)i * ld + j) * es;
+            if (dt == DT_F64) {
+                std::memcpy(dst, &v, 8);
+            } else if (dt == DT_F32) {
+                const float f = (float)v;
+                std::memcpy(dst, &f, 4);
+            } else {
+                const uint16_t h = host_bf16(v);
+                std::memcpy(dst, &h, 2);
+            }
+        }
+    void* p = nullptr;
+    if (hipMalloc(&p, buf.size()) != hipSuccess) return fail(CTA_ERR_NOMEM, "hipMalloc of a factor failed");
+    allocs.push_back(p);
+    bytes_acc += buf.size();
+    if (hipMemcpy(p, buf.data(), buf.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(CTA_ERR_HIP, "copy of a factor to the device failed");
+    out->p = p;
+    out->ld = ld;
+    out->rows = R;
+    out->cols = C;
+    return CTA_OK;
+}
+
+cta_status dev_alloc(void** p, size_t bytes, std::vector<void*>& allocs, size_t& acc) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return fail(CTA_ERR_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    allocs.push_back(*p);
+    acc += bytes;
+    return CTA_OK;
+}
+
+static int prec_tc(int prec) {
+    return prec == CTA_PREC_F64 ? DT_F64 : (prec == CTA_PREC_F32 ? DT_F32 : DT_BF16);
+}
+static int prec_tvec(int prec) { return prec == CTA_PREC_F64 ? DT_F64 : DT_F32; }
+
+// ---------------------------------------------------------------------------
+// normal operator: Q = N(P)
+//   pass A: tail on modes (N-2, N-1) of P (optionally fused with p = r + beta p)
+//   middle: strided passes on modes N-3 .. 1
+//   last  : mode 0 with the banded regulariser of P and <P, Q>
+cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post,
+                        double* dot_out, bool fuse_update, hipStream_t s) {
+    const int N = op->order;
+    const int tc = prec_tc(prec), tv = prec_tvec(prec);
+    const int* done = fuse_update ? &op->scal->done : nullptr;
+    const int a = N - 2, b = N - 1;
+    const int64_t nblk = op->N / (op->n[a] * op->n[b]);
+    if (!tail_fits(tc, (int)op->n[a], (int)op->n[b]))
+        return fail(CTA_ERR_UNSUPPORTED,
+                    "last two extents (%lld, %lld) exceed the fused-tail LDS budget for this precision",
+                    (long long)op->n[a], (long long)op->n[b]);
+    const void* Pin = P;
+    void* pvec = nullptr;
+    if (fuse_update) {
+        Pin = op->vr;   // chain input is r + beta p, written to p
+        pvec = op->vp;
+        P = op->vp;
+    }
+    hipError_t e = launch_tail(tv, tc, tc, Pin, op->T1, op->G[tc][a], op->G[tc][b], nblk,
+                               (int)op->n[a], (int)op->n[b], (int)op->n[a], (int)op->n[b], pvec,
+                               &op->scal->beta, done, s);
+    if (e != hipSuccess) return fail(CTA_ERR_HIP, "tail pass launch: %s", hipGetErrorString(e));
+    void* cur = op->T1;
+    void* nxt = op->T2;
+    for (int k = N - 3; k >= 1; --k) {
+        int64_t lead = 1, trail = 1;
+        for (int l = 0; l < k; ++l) lead *= op->n[l];
+        for (int l = k + 1; l < N; ++l) trail *= op->n[l];
+        e = launch_strided(tc, cur, nxt, op->G[tc][k], lead, (int)op->n[k], (int)op->n[k], trail,
+                           done, s);
+        if (e != hipSuccess) return fail(CTA_ERR_HIP, "mode pass launch: %s", hipGetErrorString(e));
+        std::swap(cur, nxt);
+    }
+    StencilDesc st{};
+    st.P = P;
+    st.order = N;
+    st.lam = op->lam;
+    int64_t stride = 1;
+    for (int k = N - 1; k >= 0; --k) {
+        st.ext[k] = op->n[k];
+        st.stride[k] = stride;
+        stride *= op->n[k];
+        st.rband[k] = op->rband[tv == DT_F64 ? 0 : 1][k];
+    }
+    e = launch_normal_last(tc, tv, tc, cur, Q, op->G[tc][0], (int)op->n[0], (int)op->n[0],
+                           op->N / op->n[0], st, op->partials, op->scal, post, dot_out, done, s);
+    if (e != hipSuccess) return fail(CTA_ERR_HIP, "last pass launch: %s", hipGetErrorString(e));
+    return CTA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// rectangular chain for forward / rhs / general TTM: planner + passes
+// Choose the order of the mode products minimising flops (products on
+// distinct modes commute, Sec. 2.1; Sec. 2.1 also motivates picking the order
+// that gives the least work and the smallest intermediates).
+std::vector<int> plan_order(int N, const int64_t* in_ext, const int64_t* out_ext,
+                            const std::vector<int>& modes, int64_t* max_elems) {
+    std::vector<int> perm(modes);
+    std::sort(perm.begin(), perm.end());
+    std::vector<int> best = perm;
+    double best_cost = -1;
+    int64_t best_max = 0;
+    do {
+        int64_t cur[CTA_MAX_ORDER];
+        for (int k = 0; k < N; ++k) cur[k] = in_ext[k];
+        double cost = 0;
+        int64_t tot = 1, mx = 0;
+        for (int k = 0; k < N; ++k) tot *= cur[k];
+        mx = tot;
+        for (int k : perm) {
+            cost += 2.0 * (double)(tot / cur[k]) * (double)out_ext[k] * (double)cur[k];
+            tot = tot / cur[k] * out_ext[k];
+            cur[k] = out_ext[k];
+            mx = std::max(mx, tot);
+        }
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && mx < best_max)) {
+            best_cost = cost;
+            best = perm;
+            best_max = mx;
+        }
+    } while (std::next_permutation(perm.begin(), perm.end()));
+    if (max_elems) *max_elems = best_max;
+    return best;
+}
+
+// Run the chain: X (in dtype tin) -> Y (dtype tout) using compute type tc and
+// the two work buffers (each >= max intermediate elements * size(tc)).
+cta_status run_chain(int N, const int64_t* in_ext, const int64_t* out_ext, const Mat* mats,
+                     const std::vector<int>& order, const void* X, int tin, void* Y, int tout,
+                     int tc, void* w0, void* w1, hipStream_t s) {
+    int64_t cur[CTA_MAX_ORDER];
+    int64_t tot = 1;
+    for (int k = 0; k < N; ++k) {
+        cur[k] = in_ext[k];
+        tot *= cur[k];
+    }
+    const void* src = X;
+    hipError_t e;
+    if (tin != tc || order.empty()) {
+        e = launch_cast(tin, tc, X, w0, tot, s);
+        if (e != hipSuccess) return fail(CTA_ERR_HIP, "cast launch: %s", hipGetErrorString(e));
+        src = w0;
+    }
+    if (order.empty()) {
+        e = launch_cast(tc, tout, w0, Y, tot, s);
+        if (e != hipSuccess) return fail(CTA_ERR_HIP, "cast launch: %s", hipGetErrorString(e));
+        return CTA_OK;
+    }
+    for (size_t i = 0; i < order.size(); ++i) {
+        const int k = order[i];
+        const bool last = i + 1 == order.size();
+        void* dst = (last && tout == tc) ? Y : (src == w0 ? w1 : w0);
+        int64_t lead = 1, trail = 1;
+        for (int l = 0; l < k; ++l) lead *= cur[l];
+        for (int l = k + 1; l < N; ++l) trail *= cur[l];
+        const int K = (int)cur[k], J = (int)out_ext[k];
+        if (trail == 1)
+            e = launch_contig(tc, src, dst, mats[k], lead, K, J, nullptr, s);
+        else
+            e = launch_strided(tc, src, dst, mats[k], lead, K, J, trail, nullptr, s);
+        if (e != hipSuccess) return fail(CTA_ERR_HIP, "mode %d pass launch: %s", k, hipGetErrorString(e));
+        tot = tot / cur[k] * J;
+        cur[k] = J;
+        src = dst;
+    }
+    if (src != Y) {
+        e = launch_cast(tc, tout, src, Y, tot, s);
+        if (e != hipSuccess) return fail(CTA_ERR_HIP, "cast launch: %s", hipGetErrorString(e));
+    }
+    return CTA_OK;
+}
+
+}  // namespace cta
+
+// ---------------------------------------------------------------------------
+// operator handle
+extern "C" cta_status cta_op_create(cta_op* out, int order, const int64_t* n, const int64_t* m,
+                                    const double* const* host_A, const double* const* host_D,
+                                    const int64_t* p, double lambda, void* stream) {
+    (void)stream;
+    if (!out) return fail(CTA_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (order < 2 || order > CTA_MAX_ORDER) return fail(CTA_ERR_ARG, "order %d outside [2, %d]", order, CTA_MAX_ORDER);
+    if (!n || !m || !host_A) return fail(CTA_ERR_ARG, "n, m and host_A are required");
+    if (host_D && !p) return fail(CTA_ERR_ARG, "host_D given without p");
+    if (!std::isfinite(lambda)) return fail(CTA_ERR_ARG, "lambda is not finite");
+    for (int k = 0; k < order; ++k) {
+        if (n[k] < 1 || m[k] < 1 || n[k] > CTA_MAX_EXTENT || m[k] > CTA_MAX_EXTENT)
+            return fail(CTA_ERR_SHAPE, "mode %d: extents n=%lld m=%lld outside [1, %d]", k,
+                        (long long)n[k], (long long)m[k], CTA_MAX_EXTENT);
+        if (!host_A[k]) return fail(CTA_ERR_ARG, "host_A[%d] is NULL", k);
+        if (host_D && p[k] < 0) return fail(CTA_ERR_SHAPE, "p[%d] < 0", k);
+        if (host_D && p[k] > 0 && !host_D[k]) return fail(CTA_ERR_ARG, "host_D[%d] is NULL", k);
+    }
+    cta_op_s* op = new cta_op_s();
+    // order 2 is lifted to order 3 with a leading unit mode (G = 1, no regulariser)
+    const int lift = order == 2 ? 1 : 0;
+    op->lift = lift;
+    op->user_order = order;
+    op->order = order + lift;
+    op->lam = lambda;
+    std::vector<std::vector<double>> G(op->order), A(op->order), R(op->order);
+    std::vector<bool> has_reg(op->order, false);
+    for (int k = 0; k < op->order; ++k) {
+        const int uk = k - lift;
+        if (uk < 0) {
+            op->n[k] = 1;
+            op->m[k] = 1;
+            G[k] = {1.0};
+            A[k] = {1.0};
+            continue;
+        }
+        const int64_t nk = n[uk], mk = m[uk];
+        op->n[k] = nk;
+        op->m[k] = mk;
+        A[k].assign(host_A[uk], host_A[uk] + nk * mk);
+        G[k].assign(nk * nk, 0.0);
+        for (int64_t i = 0; i < nk; ++i)
+            for (int64_t j = 0; j < nk; ++j) {
+                double sacc = 0;
+                for (int64_t r = 0; r < mk; ++r) sacc += A[k][r * nk + i] * A[k][r * nk + j];
+                G[k][i * nk + j] = sacc;
+            }
+        if (host_D && p[uk] > 0) {
+            const int64_t pk = p[uk];
+            const double* D = host_D[uk];
+            R[k].assign(nk * nk, 0.0);
+            for (int64_t i = 0; i < nk; ++i)
+                for (int64_t j = 0; j < nk; ++j) {
+                    double sacc = 0;
+                    for (int64_t r = 0; r < pk; ++r) sacc += D[r * nk + i] * D[r * nk + j];
+                    R[k][i * nk + j] = sacc;
+                }
+            for (int64_t i = 0; i < nk; ++i)
+                for (int64_t j = 0; j < nk; ++j)
+                    if (std::llabs(i - j) > 2 && R[k][i * nk + j] != 0.0) {
+                        delete op;
+                        return fail(CTA_ERR_UNSUPPORTED,
+                                    "mode %d: D_k^T D_k has half-bandwidth > 2 (only banded regularisers "
+                                    "with half-bandwidth <= 2 are supported)", uk);
+                    }
+            has_reg[k] = true;
+        }
+    }
+    op->N = 1;
+    op->Msamp = 1;
+    int64_t big = 1;
+    for (int k = 0; k < op->order; ++k) {
+        op->N *= op->n[k];
+        op->Msamp *= op->m[k];
+        big *= std::max(op->n[k], op->m[k]);
+    }
+    op->big = big;
+    cta_status st = CTA_OK;
+    auto& al = op->allocs;
+    size_t& acc = op->dev_bytes;
+    for (int k = 0; k < op->order && st == CTA_OK; ++k) {
+        const int nk = (int)op->n[k], mk = (int)op->m[k];
+        for (int dt = 0; dt < 3 && st == CTA_OK; ++dt)
+            st = upload_mat(G[k].data(), nk, nk, false, dt, &op->G[dt][k], al, acc);
+        for (int dt = 0; dt < 2 && st == CTA_OK; ++dt) {
+            st = upload_mat(A[k].data(), mk, nk, false, dt, &op->A[dt][k], al, acc);
+            if (st == CTA_OK) st = upload_mat(A[k].data(), mk, nk, true, dt, &op->At[dt][k], al, acc);
+        }
+        if (st == CTA_OK && has_reg[k]) {
+            std::vector<double> band64(nk * 5, 0.0);
+            std::vector<float> band32(nk * 5, 0.f);
+            for (int i = 0; i < nk; ++i)
+                for (int d = -2; d <= 2; ++d)
+                    if (i + d >= 0 && i + d < nk) {
+                        band64[i * 5 + d + 2] = R[k][(size_t)i * nk + i + d];
+                        band32[i * 5 + d + 2] = (float)R[k][(size_t)i * nk + i + d];
+                    }
+            st = dev_alloc(&op->rband[0][k], band64.size() * 8, al, acc);
+            if (st == CTA_OK) st = dev_alloc(&op->rband[1][k], band32.size() * 4, al, acc);
+            if (st == CTA_OK &&
+                (hipMemcpy(op->rband[0][k], band64.data(), band64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(op->rband[1][k], band32.data(), band32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+                st = fail(CTA_ERR_HIP, "copy of regulariser bands failed");
+        }
+    }
+    const size_t vb = (size_t)op->N * 8;
+    void** vecs[] = {&op->T1, &op->T2, &op->vx, &op->vr, &op->vp, &op->vq, &op->vaux};
+    for (void** v : vecs)
+        if (st == CTA_OK) st = dev_alloc(v, vb, al, acc);
+    if (st == CTA_OK) st = dev_alloc((void**)&op->scal, sizeof(CgScalars), al, acc);
+    if (st == CTA_OK) st = dev_alloc((void**)&op->partials, kMaxGrid * sizeof(double), al, acc);
+    if (st == CTA_OK && hipMemset(op->scal, 0, sizeof(CgScalars)) != hipSuccess)
+        st = fail(CTA_ERR_HIP, "hipMemset of the scalars failed");
+    if (st == CTA_OK && hipHostMalloc((void**)&op->hscal, sizeof(CgScalars), hipHostMallocDefault) != hipSuccess)
+        st = fail(CTA_ERR_NOMEM, "hipHostMalloc of the scalar mirror failed");
+    if (st != CTA_OK) {
+        std::string keep = g_err;
+        cta_op_destroy(op);
+        g_err = keep;
+        return st;
+    }
+    *out = op;
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_op_destroy(cta_op op) {
+    if (!op) return CTA_OK;
+    (void)hipDeviceSynchronize();
+    for (void* p : op->allocs) (void)hipFree(p);
+    if (op->hscal) (void)hipHostFree(op->hscal);
+    delete op;
+    return CTA_OK;
+}
+
+extern "C" size_t cta_op_device_bytes(cta_op op) { return op ? op->dev_bytes : 0; }
+
+namespace cta {
+cta_status ensure_chain_ws(cta_op_s* op) {
+    if (op->rw0) return CTA_OK;
+    cta_status st = dev_alloc(&op->rw0, (size_t)op->big * 8, op->allocs, op->dev_bytes);
+    if (st == CTA_OK) st = dev_alloc(&op->rw1, (size_t)op->big * 8, op->allocs, op->dev_bytes);
+    return st;
+}
+}  // namespace cta
+
+static cta_status check_dtype(cta_dtype d) {
+    if (d != CTA_F64 && d != CTA_F32 && d != CTA_BF16) return fail(CTA_ERR_DTYPE, "unknown dtype %d", (int)d);
+    return CTA_OK;
+}
+
+static cta_status op_chain(cta_op op, const void* X, cta_dtype xd, void* Y, cta_dtype yd,
+                           cta_precision chain, bool forward, void* stream) {
+    if (!op || !X || !Y) return fail(CTA_ERR_ARG, "NULL argument");
+    cta_status st = check_dtype(xd);
+    if (st == CTA_OK) st = check_dtype(yd);
+    if (st != CTA_OK) return st;
+    if (chain != CTA_PREC_F64 && chain != CTA_PREC_F32)
+        return fail(CTA_ERR_ARG, "forward/rhs chains run in CTA_PREC_F64 or CTA_PREC_F32");
+    st = ensure_chain_ws(op);
+    if (st != CTA_OK) return st;
+    const int tc = prec_tc(chain);
+    const int N = op->order;
+    std::vector<int> modes;
+    for (int k = op->lift; k < N; ++k) modes.push_back(k);
+    const int64_t* in_ext = forward ? op->n : op->m;
+    const int64_t* out_ext = forward ? op->m : op->n;
+    std::vector<int> order = plan_order(N, in_ext, out_ext, modes, nullptr);
+    const Mat* mats = forward ? op->A[tc == DT_F64 ? 0 : 1] : op->At[tc == DT_F64 ? 0 : 1];
+    return run_chain(N, in_ext, out_ext, mats, order, X, (int)xd, Y, (int)yd, tc, op->rw0, op->rw1,
+                     (hipStream_t)stream);
+}
+
+extern "C" cta_status cta_forward(cta_op op, const void* X, cta_dtype x_dtype, void* Y,
+                                  cta_dtype y_dtype, cta_precision chain, void* stream) {
+    return op_chain(op, X, x_dtype, Y, y_dtype, chain, true, stream);
+}
+
+extern "C" cta_status cta_rhs(cta_op op, const void* Y, cta_dtype y_dtype, void* B,
+                              cta_dtype b_dtype, cta_precision chain, void* stream) {
+    return op_chain(op, Y, y_dtype, B, b_dtype, chain, false, stream);
+}
+
+extern "C" cta_status cta_apply_normal_op(cta_op op, const void* P, void* Q, cta_dtype dtype,
+                                          cta_precision chain, double* dot, void* stream) {
+    if (!op || !P || !Q) return fail(CTA_ERR_ARG, "NULL argument");
+    if (chain != CTA_PREC_F64 && chain != CTA_PREC_F32 && chain != CTA_PREC_BF16)
+        return fail(CTA_ERR_ARG, "chain precision must be F64, F32 or BF16");
+    const int tv = prec_tvec(chain);
+    if ((int)dtype != tv)
+        return fail(CTA_ERR_DTYPE, "P/Q dtype must be %s for this chain precision",
+                    tv == DT_F64 ? "CTA_F64" : "CTA_F32");
+    if (P == Q) return fail(CTA_ERR_ARG, "P and Q must not overlap");
+    return apply_normal(op, P, Q, chain, dot ? POST_DOT : POST_NONE, dot, false, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// CG driver
+extern "C" void cta_cg_opts_default(cta_cg_opts* o) {
+    if (!o) return;
+    o->precision = CTA_PREC_F32;
+    o->rtol = 1e-6;
+    o->max_iter = 10000;
+    o->x0_given = 0;
+    o->fallback_zero = 0;
+    o->inner_rtol = 1e-2;
+    o->max_refine = 30;
+    o->check_every = 16;
+}
+
+namespace cta {
+
+static cta_status read_scal(cta_op_s* op, hipStream_t s) {
+    if (hipMemcpyAsync(op->hscal, op->scal, sizeof(CgScalars), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(CTA_ERR_HIP, "scalar readback failed");
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(CTA_ERR_HIP, "stream synchronize failed");
+    return CTA_OK;
+}
+
+#define CTA_TRY(x)                          \
+    do {                                    \
+        cta_status st_ = (x);               \
+        if (st_ != CTA_OK) return st_;      \
+    } while (0)
+#define CTA_HIP(x)                                                                  \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess) return fail(CTA_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+// Inner CG loop on the handle's vectors: x (vx or the user's X), r = vr, p = vp,
+// q = vq, with scal->rho and scal->bnorm2 already set.  Returns the final done flag.
+cta_status cg_loop(cta_op_s* op, void* x, int prec, double rtol, int max_iter, int check_every,
+                   hipStream_t s, int* done_out, int* iters_out) {
+    const int tv = prec_tvec(prec);
+    const size_t vb = (size_t)op->N * dt_size(tv);
+    CTA_HIP(launch_fill_zero(op->vp, vb, s));
+    CTA_HIP(launch_cg_setup(op->scal, rtol * rtol, max_iter, s));
+    if (check_every < 1) check_every = 1;
+    for (;;) {
+        for (int c = 0; c < check_every; ++c) {
+            CTA_TRY(apply_normal(op, nullptr, op->vq, prec, POST_ALPHA, nullptr, true, s));
+            CTA_HIP(launch_cg_update(tv, x, op->vr, op->vp, op->vq, op->N, op->partials, op->scal, s));
+        }
+        CTA_TRY(read_scal(op, s));
+        if (op->hscal->done != DONE_RUNNING) break;
+    }
+    *done_out = op->hscal->done;
+    *iters_out = op->hscal->iters;
+    return CTA_OK;
+}
+
+// FP64 residual norm ||B - N(X)||_2 for X and B of dtype tx; uses vaux, vq
+// and vr as FP64 scratch.  NaN when the FP64 chain does not fit.
+cta_status true_residual(cta_op_s* op, const void* B, const void* X, int tx, hipStream_t s,
+                         double* res) {
+    if (!tail_fits(DT_F64, (int)op->n[op->order - 2], (int)op->n[op->order - 1])) {
+        *res = NAN;
+        return CTA_OK;
+    }
+    const void* X64 = X;
+    if (tx != DT_F64) {
+        CTA_HIP(launch_cast(tx, DT_F64, X, op->vaux, op->N, s));
+        X64 = op->vaux;
+    }
+    CTA_TRY(apply_normal(op, X64, op->vq, CTA_PREC_F64, POST_NONE, nullptr, false, s));
+    const void* B64 = B;
+    if (tx != DT_F64) {
+        CTA_HIP(launch_cast(tx, DT_F64, B, op->vr, op->N, s));
+        B64 = op->vr;
+    }
+    CTA_HIP(launch_residual(DT_F64, DT_F64, B64, op->vq, op->vr, op->N, op->partials, op->scal,
+                            &op->scal->dot, s));
+    CTA_TRY(read_scal(op, s));
+    *res = std::sqrt(op->hscal->dot);
+    return CTA_OK;
+}
+
+}  // namespace cta
+
+extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype dtype,
+                                   const cta_cg_opts* opts, cta_cg_info* info, void* stream) {
+    if (!op || !B || !X || !opts || !info) return fail(CTA_ERR_ARG, "NULL argument");
+    std::memset(info, 0, sizeof *info);
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    const int prec = opts->precision;
+    if (prec < CTA_PREC_F64 || prec > CTA_PREC_BF16_REFINE) return fail(CTA_ERR_ARG, "bad precision");
+    if (!(opts->rtol >= 0) || opts->max_iter < 0) return fail(CTA_ERR_ARG, "bad rtol or max_iter");
+    const int want = (prec == CTA_PREC_F64 || prec == CTA_PREC_BF16_REFINE) ? DT_F64 : DT_F32;
+    if ((int)dtype != want)
+        return fail(CTA_ERR_DTYPE, "B and X must be %s for this precision", want == DT_F64 ? "CTA_F64" : "CTA_F32");
+    if (B == X) return fail(CTA_ERR_ARG, "B and X must not overlap");
+    const int N = op->order;
+    if (!tail_fits(prec_tc(prec == CTA_PREC_BF16_REFINE ? CTA_PREC_F64 : prec), (int)op->n[N - 2], (int)op->n[N - 1]))
+        return fail(CTA_ERR_UNSUPPORTED, "last two extents too large for the fused tail in this precision");
+    const int check = opts->check_every > 0 ? opts->check_every : 16;
+    const int64_t n = op->N;
+    int done = 0, iters = 0;
+
+    if (prec != CTA_PREC_BF16_REFINE) {
+        const int tv = prec_tvec(prec);
+        const size_t vb = (size_t)n * dt_size(tv);
+        CTA_HIP(launch_dot(tv, B, B, n, op->partials, op->scal, &op->scal->bnorm2, s));
+        if (opts->x0_given) {
+            CTA_TRY(apply_normal(op, X, op->vq, prec, POST_NONE, nullptr, false, s));
+            CTA_HIP(launch_residual(tv, tv, B, op->vq, op->vr, n, op->partials, op->scal, &op->scal->rho, s));
+            if (opts->fallback_zero) {
+                CTA_TRY(read_scal(op, s));
+                if (!(op->hscal->rho < op->hscal->bnorm2)) {
+                    CTA_HIP(launch_fill_zero(X, vb, s));
+                    CTA_HIP(launch_cast(tv, tv, B, op->vr, n, s));
+                    CTA_HIP(launch_dot(tv, B, B, n, op->partials, op->scal, &op->scal->rho, s));
+                }
+            }
+        } else {
+            CTA_HIP(launch_fill_zero(X, vb, s));
+            CTA_HIP(launch_cast(tv, tv, B, op->vr, n, s));
+            CTA_HIP(launch_dot(tv, B, B, n, op->partials, op->scal, &op->scal->rho, s));
+        }
+        CTA_TRY(cg_loop(op, X, prec, opts->rtol, opts->max_iter, check, s, &done, &iters));
+        int total = iters;
+        double rel_rec = std::sqrt(std::max(0.0, op->hscal->rho) / std::max(op->hscal->bnorm2, 1e-300));
+        double bn2 = op->hscal->bnorm2;
+        double rel_true = 0;
+        CTA_TRY(true_residual(op, B, X, tv, s, &rel_true));
+        rel_true = bn2 > 0 ? rel_true / std::sqrt(bn2) : rel_true;
+        // one restart from the recomputed residual when the recursive residual
+        // met the tolerance but the true one did not
+        if (done == DONE_CONVERGED && rel_true > opts->rtol && total < opts->max_iter) {
+            CTA_TRY(apply_normal(op, X, op->vq, prec, POST_NONE, nullptr, false, s));
+            CTA_HIP(launch_residual(tv, tv, B, op->vq, op->vr, n, op->partials, op->scal, &op->scal->rho, s));
+            CTA_HIP(launch_dot(tv, B, B, n, op->partials, op->scal, &op->scal->bnorm2, s));
+            CTA_TRY(cg_loop(op, X, prec, opts->rtol, opts->max_iter - total, check, s, &done, &iters));
+            total += iters;
+            rel_rec = std::sqrt(std::max(0.0, op->hscal->rho) / std::max(op->hscal->bnorm2, 1e-300));
+            CTA_TRY(true_residual(op, B, X, tv, s, &rel_true));
+            rel_true = bn2 > 0 ? rel_true / std::sqrt(bn2) : rel_true;
+        }
+        info->iters = total;
+        info->refine_steps = 0;
+        info->rel_res_recursive = rel_rec;
+        info->rel_res_true = rel_true;
+    } else {
+        // FP64 iterative refinement; the inner solves use the BF16 chain
+        const double rtol = opts->rtol;
+        const double eta = opts->inner_rtol > 0 ? opts->inner_rtol : 1e-2;
+        CTA_HIP(launch_dot(DT_F64, B, B, n, op->partials, op->scal, &op->scal->bnorm2, s));
+        CTA_TRY(read_scal(op, s));
+        const double bn2 = op->hscal->bnorm2;
+        if (!opts->x0_given) CTA_HIP(launch_fill_zero(X, (size_t)n * 8, s));
+        auto outer_residual = [&](double* rr) -> cta_status {
+            CTA_TRY(apply_normal(op, X, op->vq, CTA_PREC_F64, POST_NONE, nullptr, false, s));
+            CTA_HIP(launch_residual(DT_F64, DT_F32, B, op->vq, op->vr, n, op->partials, op->scal,
+                                    &op->scal->rho, s));
+            CTA_TRY(read_scal(op, s));
+            *rr = op->hscal->rho;
+            return CTA_OK;
+        };
+        double rr = 0;
+        CTA_TRY(outer_residual(&rr));
+        if (opts->x0_given && opts->fallback_zero && !(rr < bn2)) {
+            CTA_HIP(launch_fill_zero(X, (size_t)n * 8, s));
+            CTA_TRY(outer_residual(&rr));
+        }
+        int steps = 0, total = 0;
+        done = DONE_RUNNING;
+        while (true) {
+            if (!std::isfinite(rr)) {
+                done = DONE_BREAKDOWN;
+                break;
+            }
+            if (rr <= rtol * rtol * bn2) {
+                done = DONE_CONVERGED;
+                break;
+            }
+            if (steps >= opts->max_refine) {
+                done = DONE_MAXITER;
+                break;
+            }
+            // inner solve N_bf16 d = r (r in vr as FP32, rho = ||r||^2 already set)
+            CTA_HIP(launch_fill_zero(op->vx, (size_t)n * 4, s));
+            CTA_HIP(launch_dot(DT_F32, op->vr, op->vr, n, op->partials, op->scal, &op->scal->bnorm2, s));
+            int idone = 0, iit = 0;
+            CTA_TRY(cg_loop(op, op->vx, CTA_PREC_BF16, eta, opts->max_iter, check, s, &idone, &iit));
+            total += iit;
+            if (idone == DONE_BREAKDOWN && iit == 0) {
+                done = DONE_BREAKDOWN;
+                break;
+            }
+            CTA_HIP(launch_add_f64((double*)X, op->vx, DT_F32, n, s));
+            ++steps;
+            CTA_TRY(outer_residual(&rr));
+        }
+        info->iters = total;
+        info->refine_steps = steps;
+        info->rel_res_recursive = std::sqrt(std::max(0.0, rr) / std::max(bn2, 1e-300));
+        info->rel_res_true = info->rel_res_recursive;  // the outer residual is recomputed in FP64
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(CTA_ERR_HIP, "stream synchronize failed");
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    cta_status st;
+    if (done == DONE_CONVERGED)
+        st = CTA_OK;
+    else if (done == DONE_BREAKDOWN)
+        st = fail(CTA_ERR_BREAKDOWN, "CG breakdown: <p, N p> <= 0 or a non-finite scalar");
+    else
+        st = fail(CTA_NOT_CONVERGED, "tolerance not reached within the iteration limit");
+    info->status = st;
+    return st;
+}

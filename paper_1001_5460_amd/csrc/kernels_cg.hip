@@ -1,0 +1,342 @@
+// gfx950 vector kernels of the tensor CG (Fig. Tensor_CG): elementwise
+// updates (App. A.4) fused with FP64 inner products (App. A.6).
+#include <algorithm>
+
+#include "launch.hpp"
+#include "reduce.hpp"
+
+namespace cta {
+
+namespace {
+
+constexpr int kItems = 4;  // elements per thread per sweep
+
+int red_grid(int64_t n) {
+    const int64_t per = (int64_t)CTA_WG * kItems;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, kMaxGrid));
+}
+
+int plain_grid(int64_t n) {
+    const int64_t per = (int64_t)CTA_WG * kItems;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 65536));
+}
+
+template <typename T> struct V4 { typedef T __attribute__((ext_vector_type(4))) type; };
+
+// Visit elements [i, i+4) of every sweep; full groups of 4 use 16/32-byte
+// accesses when the arrays are 4-element aligned (n % 4 == 0 suffices for
+// device allocations), the ragged end is done element by element.
+#define CTA_SWEEP(n, BODY4, BODY1)                                                   \
+    for (int64_t i = ((int64_t)blockIdx.x * CTA_WG + threadIdx.x) * kItems; i < (n); \
+         i += (int64_t)gridDim.x * CTA_WG * kItems) {                               \
+        if (i + kItems <= (n) && ((n) % kItems) == 0) {                              \
+            BODY4                                                                   \
+        } else {                                                                    \
+            for (int64_t e = i; e < std::min<int64_t>(i + kItems, (n)); ++e) {       \
+                BODY1                                                               \
+            }                                                                       \
+        }                                                                           \
+    }
+
+}  // namespace
+
+// ------------------------------------------------------------------ cast
+template <typename Ti, typename To>
+__global__ __launch_bounds__(CTA_WG) void k_cast(const Ti* __restrict__ x, To* __restrict__ y,
+                                                 int64_t n) {
+    CTA_SWEEP(n,
+              {
+                  for (int u = 0; u < kItems; ++u) y[i + u] = cvt<To>(x[i + u]);
+              },
+              { y[e] = cvt<To>(x[e]); })
+}
+
+hipError_t launch_cast(int tin, int tout, const void* x, void* y, int64_t n, hipStream_t s) {
+    const int g = plain_grid(n);
+#define CTA_CAST(TI, TO, A, B)                                                              \
+    if (tin == A && tout == B) {                                                            \
+        k_cast<TI, TO><<<g, CTA_WG, 0, s>>>((const TI*)x, (TO*)y, n);                      \
+        return hipGetLastError();                                                           \
+    }
+    CTA_CAST(double, float, DT_F64, DT_F32)
+    CTA_CAST(float, double, DT_F32, DT_F64)
+    CTA_CAST(double, bf16, DT_F64, DT_BF16)
+    CTA_CAST(bf16, double, DT_BF16, DT_F64)
+    CTA_CAST(float, bf16, DT_F32, DT_BF16)
+    CTA_CAST(bf16, float, DT_BF16, DT_F32)
+    CTA_CAST(double, double, DT_F64, DT_F64)
+    CTA_CAST(float, float, DT_F32, DT_F32)
+    CTA_CAST(bf16, bf16, DT_BF16, DT_BF16)
+#undef CTA_CAST
+    return hipErrorInvalidValue;
+}
+
+__global__ __launch_bounds__(CTA_WG) void k_zero(unsigned char* p, int64_t bytes) {
+    for (int64_t i = ((int64_t)blockIdx.x * CTA_WG + threadIdx.x) * 16; i < bytes;
+         i += (int64_t)gridDim.x * CTA_WG * 16) {
+        if (i + 16 <= bytes) {
+            *reinterpret_cast<uint4*>(p + i) = make_uint4(0, 0, 0, 0);
+        } else {
+            for (int64_t e = i; e < bytes; ++e) p[e] = 0;
+        }
+    }
+}
+
+hipError_t launch_fill_zero(void* x, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0) return hipSuccess;
+    if ((reinterpret_cast<uintptr_t>(x) & 15) != 0) return hipErrorInvalidValue;
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((bytes + 4095) / 4096, 65536));
+    k_zero<<<g, CTA_WG, 0, s>>>(reinterpret_cast<unsigned char*>(x), bytes);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ axpby
+template <typename T>
+__global__ __launch_bounds__(CTA_WG) void k_axpby(T a, const T* __restrict__ x, T b,
+                                                  T* __restrict__ y, int64_t n) {
+    typedef typename V4<T>::type v4;
+    CTA_SWEEP(n,
+              {
+                  v4 xv = *reinterpret_cast<const v4*>(x + i);
+                  v4 yv = *reinterpret_cast<v4*>(y + i);
+                  *reinterpret_cast<v4*>(y + i) = a * xv + b * yv;
+              },
+              { y[e] = a * x[e] + b * y[e]; })
+}
+
+hipError_t launch_axpby(int tv, double a, const void* x, double b, void* y, int64_t n,
+                        hipStream_t s) {
+    const int g = plain_grid(n);
+    if (tv == DT_F64) {
+        k_axpby<double><<<g, CTA_WG, 0, s>>>(a, (const double*)x, b, (double*)y, n);
+    } else if (tv == DT_F32) {
+        k_axpby<float><<<g, CTA_WG, 0, s>>>((float)a, (const float*)x, (float)b, (float*)y, n);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ residual r = B - Q, <r, r>
+template <typename Tb, typename Tr>
+__global__ __launch_bounds__(CTA_WG) void k_residual(const Tb* __restrict__ B,
+                                                     const Tb* __restrict__ Q, Tr* __restrict__ r,
+                                                     int64_t n, double* partials,
+                                                     unsigned* counter, double* out) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    CTA_SWEEP(n,
+              {
+                  for (int u = 0; u < kItems; ++u) {
+                      const Tr v = cvt<Tr>(B[i + u] - Q[i + u]);
+                      r[i + u] = v;
+                      acc += (double)v * (double)v;
+                  }
+              },
+              {
+                  const Tr v = cvt<Tr>(B[e] - Q[e]);
+                  r[e] = v;
+                  acc += (double)v * (double)v;
+              })
+    double total;
+    if (grid_reduce(acc, partials, counter, red, total) && threadIdx.x == 0) *out = total;
+}
+
+hipError_t launch_residual(int tb, int tr, const void* B, const void* Q, void* r, int64_t n,
+                           double* partials, CgScalars* scal, double* out, hipStream_t s) {
+    const int g = red_grid(n);
+    unsigned* c = &scal->counter[1];
+    if (tb == DT_F64 && tr == DT_F64)
+        k_residual<double, double><<<g, CTA_WG, 0, s>>>((const double*)B, (const double*)Q,
+                                                        (double*)r, n, partials, c, out);
+    else if (tb == DT_F64 && tr == DT_F32)
+        k_residual<double, float><<<g, CTA_WG, 0, s>>>((const double*)B, (const double*)Q,
+                                                       (float*)r, n, partials, c, out);
+    else if (tb == DT_F32 && tr == DT_F32)
+        k_residual<float, float><<<g, CTA_WG, 0, s>>>((const float*)B, (const float*)Q,
+                                                      (float*)r, n, partials, c, out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ dot
+template <typename T>
+__global__ __launch_bounds__(CTA_WG) void k_dot(const T* __restrict__ x, const T* __restrict__ y,
+                                                int64_t n, double* partials, unsigned* counter,
+                                                double* out) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    CTA_SWEEP(n,
+              {
+                  for (int u = 0; u < kItems; ++u) acc += (double)x[i + u] * (double)y[i + u];
+              },
+              { acc += (double)x[e] * (double)y[e]; })
+    double total;
+    if (grid_reduce(acc, partials, counter, red, total) && threadIdx.x == 0) *out = total;
+}
+
+hipError_t launch_dot(int tv, const void* x, const void* y, int64_t n, double* partials,
+                      CgScalars* scal, double* out, hipStream_t s) {
+    const int g = red_grid(n);
+    unsigned* c = &scal->counter[2];
+    if (tv == DT_F64)
+        k_dot<double><<<g, CTA_WG, 0, s>>>((const double*)x, (const double*)y, n, partials, c, out);
+    else if (tv == DT_F32)
+        k_dot<float><<<g, CTA_WG, 0, s>>>((const float*)x, (const float*)y, n, partials, c, out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ CG step
+// C += alpha P; R -= alpha Q; rho1 = <R, R>; P's update (P = R + beta P) is
+// fused into the first pass of the next operator application.
+template <typename T>
+__global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
+                                                      const T* __restrict__ p,
+                                                      const T* __restrict__ q, int64_t n,
+                                                      double* partials, CgScalars* scal) {
+    if (scal->done) return;
+    __shared__ double red[4];
+    typedef typename V4<T>::type v4;
+    const T alpha = (T)scal->alpha;
+    double acc = 0.0;
+    CTA_SWEEP(n,
+              {
+                  v4 xv = *reinterpret_cast<v4*>(x + i);
+                  v4 rv = *reinterpret_cast<v4*>(r + i);
+                  const v4 pv = *reinterpret_cast<const v4*>(p + i);
+                  const v4 qv = *reinterpret_cast<const v4*>(q + i);
+                  xv = xv + alpha * pv;
+                  rv = rv - alpha * qv;
+                  *reinterpret_cast<v4*>(x + i) = xv;
+                  *reinterpret_cast<v4*>(r + i) = rv;
+                  for (int u = 0; u < kItems; ++u) acc += (double)rv[u] * (double)rv[u];
+              },
+              {
+                  x[e] = x[e] + alpha * p[e];
+                  const T rv = r[e] - alpha * q[e];
+                  r[e] = rv;
+                  acc += (double)rv * (double)rv;
+              })
+    double rho1;
+    if (grid_reduce(acc, partials, &scal->counter[3], red, rho1) && threadIdx.x == 0) {
+        const double rho = scal->rho;
+        scal->beta = rho1 / rho;
+        scal->rho = rho1;
+        scal->iters += 1;
+        if (!__builtin_isfinite(rho1))
+            scal->done = DONE_BREAKDOWN;
+        else if (rho1 <= scal->threshold)
+            scal->done = DONE_CONVERGED;
+        else if (scal->iters >= scal->max_iter)
+            scal->done = DONE_MAXITER;
+    }
+}
+
+hipError_t launch_cg_update(int tv, void* x, void* r, const void* p, const void* q, int64_t n,
+                            double* partials, CgScalars* scal, hipStream_t s) {
+    const int g = red_grid(n);
+    if (tv == DT_F64)
+        k_cg_update<double><<<g, CTA_WG, 0, s>>>((double*)x, (double*)r, (const double*)p,
+                                                 (const double*)q, n, partials, scal);
+    else if (tv == DT_F32)
+        k_cg_update<float><<<g, CTA_WG, 0, s>>>((float*)x, (float*)r, (const float*)p,
+                                                (const float*)q, n, partials, scal);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+__global__ void k_cg_setup(CgScalars* scal, double rtol2, int max_iter) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    scal->threshold = rtol2 * scal->bnorm2;
+    scal->rho0 = scal->rho;
+    scal->beta = 0.0;
+    scal->alpha = 0.0;
+    scal->iters = 0;
+    scal->max_iter = max_iter;
+    if (!__builtin_isfinite(scal->rho) || !__builtin_isfinite(scal->bnorm2))
+        scal->done = DONE_BREAKDOWN;
+    else if (scal->rho <= scal->threshold)
+        scal->done = DONE_CONVERGED;
+    else if (max_iter <= 0)
+        scal->done = DONE_MAXITER;
+    else
+        scal->done = DONE_RUNNING;
+}
+
+hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s) {
+    k_cg_setup<<<1, 64, 0, s>>>(scal, rtol2, max_iter);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ X64 += d
+template <typename Td>
+__global__ __launch_bounds__(CTA_WG) void k_add_f64(double* __restrict__ X,
+                                                    const Td* __restrict__ d, int64_t n) {
+    CTA_SWEEP(n,
+              {
+                  for (int u = 0; u < kItems; ++u) X[i + u] += (double)d[i + u];
+              },
+              { X[e] += (double)d[e]; })
+}
+
+hipError_t launch_add_f64(double* X, const void* d, int td, int64_t n, hipStream_t s) {
+    const int g = plain_grid(n);
+    if (td == DT_F32)
+        k_add_f64<float><<<g, CTA_WG, 0, s>>>(X, (const float*)d, n);
+    else if (td == DT_F64)
+        k_add_f64<double><<<g, CTA_WG, 0, s>>>(X, (const double*)d, n);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace cta
+
+namespace cta {
+
+// ------------------------------------------------------------------ factor padding
+// dst[i][j] (rows_st x ld, dtype To) = op(src)[i][j] for i < R, j < C, else 0,
+// where op(src) = src (rows x cols) or its transpose.
+template <typename Ti, typename To>
+__global__ __launch_bounds__(CTA_WG) void k_pad_matrix(const Ti* __restrict__ src, int rows,
+                                                       int cols, int trans, To* __restrict__ dst,
+                                                       int rows_st, int ld) {
+    const int R = trans ? cols : rows, C = trans ? rows : cols;
+    const int64_t total = (int64_t)rows_st * ld;
+    for (int64_t e = (int64_t)blockIdx.x * CTA_WG + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * CTA_WG) {
+        const int i = (int)(e / ld), j = (int)(e % ld);
+        To v = cvt<To>(0.f);
+        if (i < R && j < C) v = cvt<To>(trans ? src[(int64_t)j * cols + i] : src[(int64_t)i * cols + j]);
+        dst[e] = v;
+    }
+}
+
+hipError_t launch_pad_matrix(int tin, int tout, const void* src, int rows, int cols, int trans,
+                             void* dst, int rows_st, int ld, hipStream_t s) {
+    const int64_t total = (int64_t)rows_st * ld;
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + CTA_WG - 1) / CTA_WG, 4096));
+#define CTA_PAD(TI, TO, A, B)                                                                 \
+    if (tin == A && tout == B) {                                                              \
+        k_pad_matrix<TI, TO><<<g, CTA_WG, 0, s>>>((const TI*)src, rows, cols, trans, (TO*)dst, \
+                                                  rows_st, ld);                               \
+        return hipGetLastError();                                                             \
+    }
+    CTA_PAD(double, double, DT_F64, DT_F64)
+    CTA_PAD(double, float, DT_F64, DT_F32)
+    CTA_PAD(double, bf16, DT_F64, DT_BF16)
+    CTA_PAD(float, double, DT_F32, DT_F64)
+    CTA_PAD(float, float, DT_F32, DT_F32)
+    CTA_PAD(float, bf16, DT_F32, DT_BF16)
+    CTA_PAD(bf16, double, DT_BF16, DT_F64)
+    CTA_PAD(bf16, float, DT_BF16, DT_F32)
+    CTA_PAD(bf16, bf16, DT_BF16, DT_BF16)
+#undef CTA_PAD
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cta

@@ -1,0 +1,286 @@
+// gfx950 kernels and launchers of the mode-product passes and of the
+// normal-operator pass (see ttm.hpp for the tiling).
+#include <algorithm>
+
+#include "launch.hpp"
+#include "reduce.hpp"
+#include "ttm.hpp"
+
+namespace cta {
+
+template <int DTV> struct DType;
+template <> struct DType<DT_F64> { typedef double T; };
+template <> struct DType<DT_F32> { typedef float T; };
+template <> struct DType<DT_BF16> { typedef bf16 T; };
+
+static int grid_for(int64_t units, int cap) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(units, cap));
+}
+
+// Raise the dynamic-LDS limit of a kernel once when it needs more than 64 KiB.
+template <typename K>
+static hipError_t ensure_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// ------------------------------------------------------------------ strided
+template <typename Tin, typename Tout, typename Tc, int JT, int WJ, int CT>
+__global__ __launch_bounds__(CTA_WG) void k_strided(StridedArgs a, const int* done) {
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Tc* Xs = reinterpret_cast<Tc*>(smem);
+    double unused = 0.0;
+    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
+        strided_tile<Tin, Tout, Tc, JT, WJ, CT, false>(a, tile, Xs, nullptr, unused);
+}
+
+template <typename Tin, typename Tout, typename Tc, int JT, int WJ, int CT>
+static hipError_t go_strided(StridedArgs a, const int* done, hipStream_t s) {
+    constexpr int TN = 16 * CT * (CTA_WAVES / WJ);
+    a.ntt = (a.trail + TN - 1) / TN;
+    a.ntiles = a.lead * a.ntt;
+    const size_t lds = (size_t)TN * (a.kpad + 16 / sizeof(Tc)) * sizeof(Tc);
+    auto kern = k_strided<Tin, Tout, Tc, JT, WJ, CT>;
+    hipError_t e = ensure_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    kern<<<grid_for(a.ntiles, 65536), CTA_WG, lds, s>>>(a, done);
+    return hipGetLastError();
+}
+
+template <typename Tin, typename Tout, typename Tc>
+static hipError_t strided_T(StridedArgs a, const int* done, hipStream_t s) {
+    const int jt = (a.J + 15) / 16;
+    if (jt <= 1) return go_strided<Tin, Tout, Tc, 1, 1, 1>(a, done, s);
+    if (jt <= 2) return go_strided<Tin, Tout, Tc, 1, 2, 2>(a, done, s);
+    if (jt <= 4) return go_strided<Tin, Tout, Tc, 1, 4, 4>(a, done, s);
+    if (jt <= 6) return go_strided<Tin, Tout, Tc, 3, 2, 2>(a, done, s);
+    if (jt <= 8) return go_strided<Tin, Tout, Tc, 2, 4, 4>(a, done, s);
+    if (jt <= 12) return go_strided<Tin, Tout, Tc, 3, 4, 4>(a, done, s);
+    if (jt <= 16) return go_strided<Tin, Tout, Tc, 4, 4, 4>(a, done, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_strided(int tc, const void* X, void* Y, const Mat& M, int64_t lead, int K, int J,
+                          int64_t trail, const int* done, hipStream_t s) {
+    StridedArgs a{};
+    a.X = X; a.Y = Y; a.M = M.p; a.ldm = M.ld;
+    a.K = K; a.J = J; a.kpad = (K + dt_kstep(tc) - 1) / dt_kstep(tc) * dt_kstep(tc);
+    a.lead = lead; a.trail = trail;
+    if (a.kpad > M.ld) return hipErrorInvalidValue;
+    switch (tc) {
+        case DT_F64: return strided_T<double, double, double>(a, done, s);
+        case DT_F32: return strided_T<float, float, float>(a, done, s);
+        case DT_BF16: return strided_T<bf16, bf16, bf16>(a, done, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ normal-operator last pass
+template <typename Tmid, typename Tvec, typename Tc, int JT, int WJ, int CT>
+__global__ __launch_bounds__(CTA_WG) void k_normal_last(StridedArgs a, StencilArgs<Tvec> st,
+                                                        CgScalars* scal, int post, double* dot_out,
+                                                        const int* done) {
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[4];
+    Tc* Xs = reinterpret_cast<Tc*>(smem);
+    double dot = 0.0;
+    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
+        strided_tile<Tmid, Tvec, Tc, JT, WJ, CT, true>(a, tile, Xs, &st, dot);
+    double total = 0.0;
+    if (grid_reduce(dot, st.partials, &scal->counter[0], red, total) && threadIdx.x == 0) {
+        if (post == POST_DOT) {
+            *dot_out = total;
+        } else if (post == POST_ALPHA) {
+            scal->pq = total;
+            if (!(total > 0.0) || !__builtin_isfinite(total))
+                scal->done = DONE_BREAKDOWN;
+            else
+                scal->alpha = scal->rho / total;
+        }
+    }
+}
+
+template <typename Tmid, typename Tvec, typename Tc, int JT, int WJ, int CT>
+static hipError_t go_last(StridedArgs a, const StencilArgs<Tvec>& st, CgScalars* scal, int post,
+                          double* dot_out, const int* done, hipStream_t s) {
+    constexpr int TN = 16 * CT * (CTA_WAVES / WJ);
+    a.ntt = (a.trail + TN - 1) / TN;
+    a.ntiles = a.lead * a.ntt;
+    const size_t lds = (size_t)TN * (a.kpad + 16 / sizeof(Tc)) * sizeof(Tc);
+    auto kern = k_normal_last<Tmid, Tvec, Tc, JT, WJ, CT>;
+    hipError_t e = ensure_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    kern<<<grid_for(a.ntiles, kMaxGrid), CTA_WG, lds, s>>>(a, st, scal, post, dot_out, done);
+    return hipGetLastError();
+}
+
+template <typename Tmid, typename Tvec, typename Tc>
+static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, CgScalars* scal,
+                         int post, double* dot_out, const int* done, hipStream_t s) {
+    StencilArgs<Tvec> st{};
+    st.P = reinterpret_cast<const Tvec*>(d.P);
+    for (int k = 0; k < 8; ++k) {
+        st.rband[k] = reinterpret_cast<const Tvec*>(d.rband[k]);
+        st.ext[k] = d.ext[k];
+        st.stride[k] = d.stride[k];
+    }
+    st.order = d.order;
+    st.lam = d.lam;
+    st.partials = partials;
+    const int jt = (a.J + 15) / 16;
+    if (jt <= 1) return go_last<Tmid, Tvec, Tc, 1, 1, 1>(a, st, scal, post, dot_out, done, s);
+    if (jt <= 2) return go_last<Tmid, Tvec, Tc, 1, 2, 2>(a, st, scal, post, dot_out, done, s);
+    if (jt <= 4) return go_last<Tmid, Tvec, Tc, 1, 4, 4>(a, st, scal, post, dot_out, done, s);
+    if (jt <= 6) return go_last<Tmid, Tvec, Tc, 3, 2, 2>(a, st, scal, post, dot_out, done, s);
+    if (jt <= 8) return go_last<Tmid, Tvec, Tc, 2, 4, 4>(a, st, scal, post, dot_out, done, s);
+    if (jt <= 12) return go_last<Tmid, Tvec, Tc, 3, 4, 4>(a, st, scal, post, dot_out, done, s);
+    if (jt <= 16) return go_last<Tmid, Tvec, Tc, 4, 4, 4>(a, st, scal, post, dot_out, done, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q, const Mat& M,
+                              int K, int J, int64_t trail, const StencilDesc& st,
+                              double* partials, CgScalars* scal, int post, double* dot_out,
+                              const int* done, hipStream_t s) {
+    StridedArgs a{};
+    a.X = X; a.Y = Q; a.M = M.p; a.ldm = M.ld;
+    a.K = K; a.J = J; a.kpad = (K + dt_kstep(tc) - 1) / dt_kstep(tc) * dt_kstep(tc);
+    a.lead = 1; a.trail = trail;
+    if (a.kpad > M.ld || K != J) return hipErrorInvalidValue;
+    if (tmid == DT_BF16 && tvec == DT_F32 && tc == DT_BF16)
+        return last_T<bf16, float, bf16>(a, st, partials, scal, post, dot_out, done, s);
+    if (tmid == DT_F32 && tvec == DT_F32 && tc == DT_F32)
+        return last_T<float, float, float>(a, st, partials, scal, post, dot_out, done, s);
+    if (tmid == DT_F64 && tvec == DT_F64 && tc == DT_F64)
+        return last_T<double, double, double>(a, st, partials, scal, post, dot_out, done, s);
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ tail
+template <typename Tin, typename Tout, typename Tc, int J2T, bool FUSE_P>
+__global__ __launch_bounds__(CTA_WG) void k_tail(TailArgs a) {
+    if (a.done && *a.done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Tc* Zt = reinterpret_cast<Tc*>(smem);
+    for (int64_t blk = blockIdx.x; blk < a.nblk; blk += gridDim.x)
+        tail_block<Tin, Tout, Tc, J2T, FUSE_P>(a, blk, Zt);
+}
+
+// K1 is padded to the MFMA K step and to the 16-row tiles of the first step.
+static int tail_k1pad(int tc, int K1) {
+    const int g = std::max(dt_kstep(tc), 16);
+    return (K1 + g - 1) / g * g;
+}
+
+static size_t tail_lds(int tc, int K1, int J2) {
+    const int k1pad = tail_k1pad(tc, K1);
+    const int j2t = (J2 + 15) / 16;
+    return (size_t)j2t * 16 * (k1pad + 16 / dt_size(tc)) * dt_size(tc);
+}
+
+bool tail_fits(int tc, int K1, int J2) {
+    return J2 <= 256 && K1 <= 256 && tail_lds(tc, K1, J2) <= 64 * 1024;
+}
+
+template <typename Tin, typename Tout, typename Tc, bool FUSE_P>
+static hipError_t tail_T(const TailArgs& a, size_t lds, hipStream_t s) {
+    const int j2t = (a.J2 + 15) / 16;
+    const int grid = grid_for(a.nblk, 65536);
+#define CTA_TAIL_GO(N)                                                          \
+    {                                                                           \
+        auto kern = k_tail<Tin, Tout, Tc, N, FUSE_P>;                           \
+        hipError_t e = ensure_lds(kern, lds);                                   \
+        if (e != hipSuccess) return e;                                          \
+        kern<<<grid, CTA_WG, lds, s>>>(a);                                      \
+        return hipGetLastError();                                               \
+    }
+    if (j2t <= 2) CTA_TAIL_GO(2)
+    if (j2t <= 4) CTA_TAIL_GO(4)
+    if (j2t <= 8) CTA_TAIL_GO(8)
+    if (j2t <= 16) CTA_TAIL_GO(16)
+#undef CTA_TAIL_GO
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const Mat& M1,
+                       const Mat& M2, int64_t nblk, int K1, int K2, int J1, int J2, void* Pvec,
+                       const double* beta, const int* done, hipStream_t s) {
+    if (!tail_fits(tc, K1, J2)) return hipErrorInvalidValue;
+    const int ks = dt_kstep(tc);
+    TailArgs a{};
+    a.X = X; a.Y = Y; a.M1 = M1.p; a.M2 = M2.p; a.ldm1 = M1.ld; a.ldm2 = M2.ld;
+    a.K1 = K1; a.K2 = K2; a.J1 = J1; a.J2 = J2;
+    a.k1pad = tail_k1pad(tc, K1);
+    a.k2pad = (K2 + ks - 1) / ks * ks;
+    a.nblk = nblk; a.Pvec = Pvec; a.beta = beta; a.done = done;
+    if (a.k1pad > M1.ld || a.k2pad > M2.ld) return hipErrorInvalidValue;
+    const size_t lds = tail_lds(tc, K1, J2);
+    const bool fuse = Pvec != nullptr;
+    if (tin == DT_F32 && tout == DT_BF16 && tc == DT_BF16)
+        return fuse ? tail_T<float, bf16, bf16, true>(a, lds, s)
+                    : tail_T<float, bf16, bf16, false>(a, lds, s);
+    if (tin == DT_F32 && tout == DT_F32 && tc == DT_F32)
+        return fuse ? tail_T<float, float, float, true>(a, lds, s)
+                    : tail_T<float, float, float, false>(a, lds, s);
+    if (tin == DT_F64 && tout == DT_F64 && tc == DT_F64)
+        return fuse ? tail_T<double, double, double, true>(a, lds, s)
+                    : tail_T<double, double, double, false>(a, lds, s);
+    if (!fuse && tin == DT_BF16 && tout == DT_BF16 && tc == DT_BF16)
+        return tail_T<bf16, bf16, bf16, false>(a, lds, s);
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ contiguous
+template <typename Tin, typename Tout, typename Tc, int JT>
+__global__ __launch_bounds__(CTA_WG) void k_contig(ContigArgs a, const int* done) {
+    if (done && *done) return;
+    const int64_t nrt = (a.rows + 15) / 16;
+    const int wave = threadIdx.x >> 6;
+    for (int64_t rt = (int64_t)blockIdx.x * CTA_WAVES + wave; rt < nrt;
+         rt += (int64_t)gridDim.x * CTA_WAVES)
+        contig_rows<Tin, Tout, Tc, JT>(a, rt);
+}
+
+template <typename Tc>
+static hipError_t contig_T(ContigArgs a, const int* done, hipStream_t s) {
+    const int64_t nrt = (a.rows + 15) / 16;
+    const int grid = grid_for((nrt + CTA_WAVES - 1) / CTA_WAVES, 65536);
+    const int jt = (a.J + 15) / 16;
+    if (jt <= 1) {
+        a.j0 = 0;
+        k_contig<Tc, Tc, Tc, 1><<<grid, CTA_WG, 0, s>>>(a, done);
+        return hipGetLastError();
+    }
+    if (jt <= 2) {
+        a.j0 = 0;
+        k_contig<Tc, Tc, Tc, 2><<<grid, CTA_WG, 0, s>>>(a, done);
+        return hipGetLastError();
+    }
+    for (int j0 = 0; j0 < a.J; j0 += 64) {
+        a.j0 = j0;
+        k_contig<Tc, Tc, Tc, 4><<<grid, CTA_WG, 0, s>>>(a, done);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_contig(int tc, const void* X, void* Y, const Mat& M, int64_t rows, int K, int J,
+                         const int* done, hipStream_t s) {
+    ContigArgs a{};
+    a.X = X; a.Y = Y; a.M = M.p; a.ldm = M.ld;
+    a.K = K; a.J = J; a.kpad = (K + dt_kstep(tc) - 1) / dt_kstep(tc) * dt_kstep(tc);
+    a.rows = rows;
+    if (a.kpad > M.ld) return hipErrorInvalidValue;
+    switch (tc) {
+        case DT_F64: return contig_T<double>(a, done, s);
+        case DT_F32: return contig_T<float>(a, done, s);
+        case DT_BF16: return contig_T<bf16>(a, done, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cta

@@ -1,0 +1,96 @@
+// Host-side launchers of the gfx950 kernels (internal interface of libcta).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cta {
+
+enum DT { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+inline int dt_size(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2); }
+// K granularity of the MFMA instruction used for a compute type
+inline int dt_kstep(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 16 : 32); }
+
+// A factor matrix on the device in one compute type, zero padded to
+// rows_st = roundup(rows, 64), ld = roundup(cols, 32).
+struct Mat {
+    const void* p = nullptr;
+    int ld = 0;
+    int rows = 0, cols = 0;
+};
+
+// Device scalars of one CG solve (FP64).
+struct CgScalars {
+    double rho;        // <r, r> of the current residual
+    double pq;         // <p, N p>
+    double alpha, beta;
+    double threshold;  // (rtol * ||B||)^2
+    double bnorm2;     // ||B||^2
+    double rho0;
+    double dot;        // result slot of stand-alone dots
+    int iters;
+    int done;          // 0 running, 1 converged, 2 breakdown, 3 iteration limit
+    int max_iter;
+    int pad0;
+    unsigned counter[4];  // arrival counters of grid reductions (kept at zero between launches)
+};
+
+enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_BREAKDOWN = 2, DONE_MAXITER = 3 };
+
+// Banded regulariser of the normal operator (half-bandwidth <= 2).
+struct StencilDesc {
+    const void* P;
+    const void* rband[8];
+    int64_t ext[8];
+    int64_t stride[8];
+    int order;
+    double lam;
+};
+
+// Post-processing done by the last workgroup of the normal-operator pass.
+enum { POST_NONE = 0, POST_DOT = 1, POST_ALPHA = 2 };
+
+// Maximum grid of the tile-loop kernels (and size of the partials array).
+constexpr int kMaxGrid = 4096;
+
+// ---- TTM passes ----
+hipError_t launch_strided(int tc, const void* X, void* Y, const Mat& M, int64_t lead, int K, int J,
+                          int64_t trail, const int* done, hipStream_t s);
+hipError_t launch_contig(int tc, const void* X, void* Y, const Mat& M, int64_t rows, int K, int J,
+                         const int* done, hipStream_t s);
+bool tail_fits(int tc, int K1, int J2);
+hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const Mat& M1,
+                       const Mat& M2, int64_t nblk, int K1, int K2, int J1, int J2, void* Pvec,
+                       const double* beta, const int* done, hipStream_t s);
+// Last pass of the normal operator: Q = X x_1 M (mode 1 of a (K, trail)
+// tensor) + banded regulariser of P, with the FP64 <P, Q> reduced on device.
+hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q, const Mat& M,
+                              int K, int J, int64_t trail, const StencilDesc& st,
+                              double* partials, CgScalars* scal, int post, double* dot_out,
+                              const int* done, hipStream_t s);
+
+// ---- vector kernels (Tv = F32 or F64) ----
+hipError_t launch_cast(int tin, int tout, const void* x, void* y, int64_t n, hipStream_t s);
+hipError_t launch_fill_zero(void* x, int64_t bytes, hipStream_t s);
+// y = a*x + b*y in type tv
+hipError_t launch_axpby(int tv, double a, const void* x, double b, void* y, int64_t n,
+                        hipStream_t s);
+// r = B - Q (tb: dtype of B and Q; tr: dtype of r); returns <r, r> into scal->rho via reduction
+hipError_t launch_residual(int tb, int tr, const void* B, const void* Q, void* r, int64_t n,
+                           double* partials, CgScalars* scal, double* out, hipStream_t s);
+// out = <x, y> (FP64, deterministic two-stage reduction)
+hipError_t launch_dot(int tv, const void* x, const void* y, int64_t n, double* partials,
+                      CgScalars* scal, double* out, hipStream_t s);
+// x += alpha p; r -= alpha q; rho1 = <r, r>; beta, convergence test (CG step)
+hipError_t launch_cg_update(int tv, void* x, void* r, const void* p, const void* q, int64_t n,
+                            double* partials, CgScalars* scal, hipStream_t s);
+// CG setup from device dots: threshold, rho, beta = 0, done flag
+hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s);
+// padded copy of a (possibly transposed) device matrix in another dtype
+hipError_t launch_pad_matrix(int tin, int tout, const void* src, int rows, int cols, int trans,
+                             void* dst, int rows_st, int ld, hipStream_t s);
+// X64 += (double) d32
+hipError_t launch_add_f64(double* X, const void* d, int td, int64_t n, hipStream_t s);
+
+}  // namespace cta
