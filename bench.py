@@ -1,0 +1,296 @@
+#!/usr/bin/env python3
+"""Headline benchmark: the 4-D 128x128x96x24 regularised tensor equation
+(37,748,736 unknowns, collocation factors 192x128, 192x128, 144x96, 36x24,
+lambda = 1e-4) solved to 1e-8 relative residual on one MI355X.
+
+One step = one pass of the whole hot path over one input tensor Y already in
+HBM: the right-hand side B = Y x_k A_k^T (FP64 chain), then FP64 iterative
+refinement whose inner tensor CG (Fig. Tensor_CG) applies the normal operator
+as a BF16 MFMA chain of mode products with FP32 vectors and FP64 dots, with
+FP64 residual recomputation on the GPU, until ||B - N(X)|| <= 1e-8 ||B||.
+
+Printed: one JSON line.  `value` = CG iterations per second over the timed
+steps (all inner iterations of the refinement); also the time to 1e-8, the
+TTM-chain TFLOP/s (2 * N * sum_k n_k flops per operator apply, plus the
+right-hand-side chain), the dominant kernel's roofline fraction (timed live
+with HIP events by the library's tracer), the oracle timed on the host, the
+plain FP32 CG comparison and the oracle's FP64 residual judge of the solution.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = ("CG iters/s + time to 1e-8 residual, 4D 128×128×96×24; "
+          "TTM-chain TFLOP/s")
+HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+# copy-kernel calibration of the rocprofv3 FETCH_SIZE / WRITE_SIZE counters and the
+# traffic of the dominant kernel, both from profiles/ (None until measured)
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_normal_last_bf16_128x128x96x24.json")
+
+
+def chain_flops_rect(in_ext, out_ext):
+    """Least flops of a rectangular mode-product chain over all orders."""
+    best = None
+    for perm in itertools.permutations(range(len(in_ext))):
+        cur = list(in_ext)
+        tot = int(np.prod(cur))
+        f = 0
+        for k in perm:
+            f += 2 * (tot // cur[k]) * out_ext[k] * cur[k]
+            tot = tot // cur[k] * out_ext[k]
+            cur[k] = out_ext[k]
+        best = f if best is None else min(best, f)
+    return best
+
+
+def algorithmic(name, N, n):
+    """(bytes, flops) one launch of a kernel class moves / does on this workload.
+
+    Bytes count each tensor the kernel must read or write once (no re-reads);
+    flops count the dense mode products (2 * N * K per mode) as the method
+    defines them.
+    """
+    sn = sum(n)
+    table = {
+        # BF16 inner CG: p = r + beta p fused into the tail (reads r, p; writes p, T1 bf16)
+        "tail_p.bf16": (N * (4 + 4 + 4 + 2), 2 * N * (n[2] + n[3])),
+        "strided.bf16": (N * (2 + 2), 2 * N * n[1]),
+        # reads T (bf16) and P (f32), writes Q (f32); banded regulariser + <P,Q>
+        "normal_last.bf16": (N * (2 + 4 + 4), 2 * N * n[0]),
+        "cg_update.f32": (N * (4 * 4 + 2 * 4), 0),
+        "tail.f64": (N * (8 + 8), 2 * N * (n[2] + n[3])),
+        "strided.f64": (N * (8 + 8), 2 * N * n[1]),
+        "normal_last.f64": (N * (8 + 8 + 8), 2 * N * n[0]),
+        "residual.f64_f32": (N * (8 + 8 + 4), 0),
+        "add_f64": (N * (8 + 4 + 8), 0),
+        "dot.f32": (N * 4, 0),
+        "dot.f64": (N * 8, 0),
+        "fill_zero": (N * 4, 0),
+    }
+    return table.get(name)
+
+
+def ensure_library():
+    import paper_1001_5460_amd as cta
+    if not os.path.exists(cta.library_path()):
+        raise SystemExit("libcta.so is not built: run `python -m paper_1001_5460_amd.build` first")
+    cta.load_library()
+    return cta
+
+
+def cpu_baseline(p, X_gpu_host, iters=3):
+    """The FP64 oracle on the host cores: a few CG iterations of the full problem,
+    plus the oracle's residual judge of the GPU solution (both outside the timed region)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    op = oracle.NormalOperator(p.A, p.D, p.lam)
+    Y = op.forward(p.X_true) + p.noise
+    B = op.rhs(Y)
+    t0 = time.perf_counter()
+    res = oracle.cg(op, B, rtol=0.0, max_iter=iters, restart=False)
+    dt = time.perf_counter() - t0
+    judge = oracle.relative_residual(X_gpu_host, B, op)
+    base = {
+        "value": res.iters / dt,
+        "unit": "CG iters/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": (f"oracle.cg, {res.iters} FP64 iterations from zero on the full "
+                   "128x128x96x24 problem (includes its initial residual and final "
+                   "residual recomputation), NumPy/BLAS on the host"),
+        "seconds": dt,
+    }
+    return base, judge
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inner-rtol", type=float, default=1e-2)
+    ap.add_argument("--max-inner", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build solves on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design in DESIGN.md, not code)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+    cta = ensure_library()
+    import workload
+
+    p = workload.config_problem(2)
+    n = p.n
+    N = int(np.prod(n))
+    dev = torch.device("cuda:0")
+    op = cta.Operator(p.A, p.D, p.lam)
+    # input data in HBM: Y = X_true x_k A_k + noise, formed on the GPU (FP64)
+    Xt = torch.from_numpy(p.X_true).to(dev)
+    Y = op.forward(Xt, chain="f64")
+    Y += torch.from_numpy(p.noise).to(dev)
+    del Xt
+    B = torch.empty(n, dtype=torch.float64, device=dev)
+    X = torch.empty(n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        op.rhs(Y, B, chain="f64")
+        _, info = op.solve(B, X, precision="bf16_refine", rtol=1e-8, inner_rtol=args.inner_rtol,
+                           max_iter=args.max_inner, max_refine=40, check_every=16)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    cta.cta_prof_reset()
+    cta.cta_prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cta.cta_prof_enable(False)
+    prof = cta.cta_prof_read()
+    cta.cta_prof_reset()
+
+    iters = sum(i["iters"] for i in infos)
+    refine = sum(i["refine_steps"] for i in infos)
+    ok = all(i["status"] == 0 and i["rel_res_true"] <= 1e-8 for i in infos)
+    sn = sum(n)
+    apply_flops = 2 * N * sn
+    rhs_flops = chain_flops_rect(p.m, p.n)
+    # BF16 applies = inner iterations; FP64 applies = one per refinement step + the initial residual
+    chain_flops = iters * apply_flops + (refine + args.steps) * apply_flops + args.steps * rhs_flops
+    chain_kernels = [k for k in prof if k.split(".")[0] in ("tail_p", "tail", "strided", "normal_last", "contig")]
+    chain_ms = sum(prof[k]["total_ms"] for k in chain_kernels)
+
+    # dominant kernel: largest total time in the timed region
+    dom = max(prof, key=lambda k: prof[k]["total_ms"])
+    avg_s = prof[dom]["total_ms"] / prof[dom]["count"] / 1e3
+    alg = algorithmic(dom, N, n)
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            with open(TRAFFIC_FILE) as f:
+                tj = json.load(f)
+            if tj.get("kernel") == dom:
+                traffic = tj.get("traffic_bytes_per_launch")
+        except Exception:
+            traffic = None
+    if alg is not None and alg[0] > 0 and not dom.endswith(".f64"):
+        achieved = alg[0] / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": alg[0], "avg_launch_ms": round(avg_s * 1e3, 4),
+                "launches": prof[dom]["count"]}
+    elif alg is not None:
+        achieved = alg[1] / avg_s / 1e12
+        roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
+                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic,
+                "algorithmic_flops_per_launch": alg[1], "avg_launch_ms": round(avg_s * 1e3, 4),
+                "launches": prof[dom]["count"]}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None, "traffic": traffic}
+
+    kernels = {}
+    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
+        a = algorithmic(k, N, n)
+        avg = v["total_ms"] / v["count"]
+        e = {"count": v["count"], "avg_ms": round(avg, 4), "share": round(v["total_ms"] / (elapsed * 1e3), 4)}
+        if a and a[0]:
+            e["GB/s"] = round(a[0] / (avg / 1e3) / 1e9, 1)
+        if a and a[1]:
+            e["TFLOP/s"] = round(a[1] / (avg / 1e3) / 1e12, 2)
+        kernels[k] = e
+
+    out = {
+        "metric": METRIC,
+        "value": round(iters / elapsed, 2),
+        "unit": "CG iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "precision": "BF16 MFMA chain (FP32 accumulate, FP32 vectors, FP64 dots) inside FP64 iterative refinement",
+        "data": "synthetic",
+        "config": {"workload": "4d_128x128x96x24_bf16_refine_to_1e-8", "unknowns": N,
+                   "samples": int(np.prod(p.m)), "lambda": p.lam, "rtol": 1e-8,
+                   "inner_rtol": args.inner_rtol, "parallelism": "single-gpu"},
+        "time_to_1e-8_s": round(elapsed / args.steps, 4),
+        "iters_per_solve": iters / args.steps,
+        "refine_steps_per_solve": refine / args.steps,
+        "rel_res_true": max(i["rel_res_true"] for i in infos),
+        "converged": ok,
+        "ttm_chain_tflops": round(chain_flops / elapsed / 1e12, 2),
+        "ttm_chain_tflops_in_kernels": round(chain_flops / (chain_ms / 1e3) / 1e12, 2) if chain_ms else None,
+        "roofline": roof,
+        "kernels": kernels,
+    }
+
+    if not args.no_compare:
+        # plain FP32 CG on the same right-hand side (outside the timed region)
+        B32 = B.float()
+        cmp = {}
+        for tol in (1e-6, 1e-8):
+            X32 = torch.empty(n, dtype=torch.float32, device=dev)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = op.solve(B32, X32, precision="f32", rtol=tol, max_iter=3000, check_every=16)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            cmp[f"{tol:g}"] = {"seconds": round(dt, 4), "iters": info["iters"], "status": info["status"],
+                               "rel_res_true": info["rel_res_true"],
+                               "iters_per_s": round(info["iters"] / dt, 2)}
+        # mixed precision to 1e-6 for a like-for-like time comparison
+        X6 = torch.empty(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info6 = op.solve(B, X6, precision="bf16_refine", rtol=1e-6, inner_rtol=args.inner_rtol,
+                            max_iter=args.max_inner, max_refine=40)
+        torch.cuda.synchronize()
+        dt6 = time.perf_counter() - t
+        out["compare_fp32"] = {
+            "fp32_cg": cmp,
+            "bf16_refine_1e-6_s": round(dt6, 4),
+            "speedup_vs_fp32_at_1e-6": round(cmp["1e-06"]["seconds"] / dt6, 3),
+            "speedup_vs_fp32_at_1e-8": (round(cmp["1e-08"]["seconds"] / out["time_to_1e-8_s"], 3)
+                                        if cmp["1e-08"]["status"] == 0 else None),
+            "fp32_reaches_1e-8": cmp["1e-08"]["status"] == 0,
+        }
+
+    if not args.no_cpu_baseline:
+        base, judge = cpu_baseline(p, X.cpu().numpy())
+        out["cpu_baseline"] = base
+        out["parity"] = {"oracle_rel_residual_of_gpu_solution": judge, "tolerance": 1e-8 * 1.01,
+                         "ok": judge <= 1e-8 * 1.01}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -260,6 +260,20 @@ cta_status cta_ws_adam_step(cta_ws w, float lr, float beta1, float beta2, float 
  * `bytes` must equal 4 * cta_ws_num_params.  Synchronous. */
 cta_status cta_ws_params(cta_ws w, void* host_buf, size_t bytes, int set, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing tracer.  When enabled, every kernel the library launches is
+ * bracketed by two HIP events recorded on the launch's stream (so the timing
+ * is of the kernel as it ran inside the caller's work).  cta_prof_read
+ * synchronises the recorded events and writes a JSON object
+ * {"<kernel>": {"count", "total_ms", "min_ms", "max_ms"}, ...} into host_buf
+ * (NUL terminated, truncated to bytes; the full length is returned in
+ * *needed).  cta_prof_reset drops the records.  Process-wide; not meant for
+ * concurrent use from several threads.
+ * ---------------------------------------------------------------------- */
+cta_status cta_prof_enable(int on);
+cta_status cta_prof_reset(void);
+cta_status cta_prof_read(char* host_buf, size_t bytes, size_t* needed);
+
 #ifdef __cplusplus
 }
 #endif

@@ -89,6 +89,10 @@ _SIGS = {
     "cta_ws_adam_step": (ctypes.c_int, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, _P]),
     "cta_ws_params": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int, _P]),
+    "cta_prof_enable": (ctypes.c_int, [ctypes.c_int]),
+    "cta_prof_reset": (ctypes.c_int, []),
+    "cta_prof_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t,
+                                     ctypes.POINTER(ctypes.c_size_t)]),
 }
 
 
@@ -396,6 +400,25 @@ def cta_ws_params(h, host=None, set=0, stream=None):
     _check(load_library().cta_ws_params(h, ctypes.c_void_p(buf.ctypes.data), 4 * n, set,
                                         _stream(stream)))
     return buf
+
+
+def cta_prof_enable(on=True):
+    _check(load_library().cta_prof_enable(int(bool(on))))
+
+
+def cta_prof_reset():
+    _check(load_library().cta_prof_reset())
+
+
+def cta_prof_read():
+    """Per-kernel totals recorded by the tracer: {name: {count, total_ms, min_ms, max_ms}}."""
+    import json
+    lib = load_library()
+    need = ctypes.c_size_t(0)
+    _check(lib.cta_prof_read(None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value + 1)
+    _check(lib.cta_prof_read(buf, need.value + 1, ctypes.byref(need)))
+    return json.loads(buf.value.decode())
 
 
 class Operator:

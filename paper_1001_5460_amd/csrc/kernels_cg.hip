@@ -3,6 +3,7 @@
 #include <algorithm>
 
 #include "launch.hpp"
+#include "prof.hpp"
 #include "reduce.hpp"
 
 namespace cta {
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(CTA_WG) void k_cast(const Ti* __restrict__ x, To* _
 
 hipError_t launch_cast(int tin, int tout, const void* x, void* y, int64_t n, hipStream_t s) {
     const int g = plain_grid(n);
+    ProfScope ps("cast", s);
 #define CTA_CAST(TI, TO, A, B)                                                              \
     if (tin == A && tout == B) {                                                            \
         k_cast<TI, TO><<<g, CTA_WG, 0, s>>>((const TI*)x, (TO*)y, n);                      \
@@ -86,6 +88,7 @@ hipError_t launch_fill_zero(void* x, int64_t bytes, hipStream_t s) {
     if (bytes <= 0) return hipSuccess;
     if ((reinterpret_cast<uintptr_t>(x) & 15) != 0) return hipErrorInvalidValue;
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((bytes + 4095) / 4096, 65536));
+    ProfScope ps("fill_zero", s);
     k_zero<<<g, CTA_WG, 0, s>>>(reinterpret_cast<unsigned char*>(x), bytes);
     return hipGetLastError();
 }
@@ -107,6 +110,7 @@ __global__ __launch_bounds__(CTA_WG) void k_axpby(T a, const T* __restrict__ x, 
 hipError_t launch_axpby(int tv, double a, const void* x, double b, void* y, int64_t n,
                         hipStream_t s) {
     const int g = plain_grid(n);
+    ProfScope ps("axpby", s);
     if (tv == DT_F64) {
         k_axpby<double><<<g, CTA_WG, 0, s>>>(a, (const double*)x, b, (double*)y, n);
     } else if (tv == DT_F32) {
@@ -146,6 +150,7 @@ hipError_t launch_residual(int tb, int tr, const void* B, const void* Q, void* r
                            double* partials, CgScalars* scal, double* out, hipStream_t s) {
     const int g = red_grid(n);
     unsigned* c = &scal->counter[1];
+    ProfScope ps(tb == DT_F64 ? (tr == DT_F64 ? "residual.f64" : "residual.f64_f32") : "residual.f32", s);
     if (tb == DT_F64 && tr == DT_F64)
         k_residual<double, double><<<g, CTA_WG, 0, s>>>((const double*)B, (const double*)Q,
                                                         (double*)r, n, partials, c, out);
@@ -180,6 +185,7 @@ hipError_t launch_dot(int tv, const void* x, const void* y, int64_t n, double* p
                       CgScalars* scal, double* out, hipStream_t s) {
     const int g = red_grid(n);
     unsigned* c = &scal->counter[2];
+    ProfScope ps(tv == DT_F64 ? "dot.f64" : "dot.f32", s);
     if (tv == DT_F64)
         k_dot<double><<<g, CTA_WG, 0, s>>>((const double*)x, (const double*)y, n, partials, c, out);
     else if (tv == DT_F32)
@@ -238,6 +244,7 @@ __global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __re
 hipError_t launch_cg_update(int tv, void* x, void* r, const void* p, const void* q, int64_t n,
                             double* partials, CgScalars* scal, hipStream_t s) {
     const int g = red_grid(n);
+    ProfScope ps(tv == DT_F64 ? "cg_update.f64" : "cg_update.f32", s);
     if (tv == DT_F64)
         k_cg_update<double><<<g, CTA_WG, 0, s>>>((double*)x, (double*)r, (const double*)p,
                                                  (const double*)q, n, partials, scal);
@@ -268,6 +275,7 @@ __global__ void k_cg_setup(CgScalars* scal, double rtol2, int max_iter) {
 }
 
 hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s) {
+    ProfScope ps("cg_setup", s);
     k_cg_setup<<<1, 64, 0, s>>>(scal, rtol2, max_iter);
     return hipGetLastError();
 }
@@ -285,6 +293,7 @@ __global__ __launch_bounds__(CTA_WG) void k_add_f64(double* __restrict__ X,
 
 hipError_t launch_add_f64(double* X, const void* d, int td, int64_t n, hipStream_t s) {
     const int g = plain_grid(n);
+    ProfScope ps("add_f64", s);
     if (td == DT_F32)
         k_add_f64<float><<<g, CTA_WG, 0, s>>>(X, (const float*)d, n);
     else if (td == DT_F64)
@@ -320,6 +329,7 @@ hipError_t launch_pad_matrix(int tin, int tout, const void* src, int rows, int c
                              void* dst, int rows_st, int ld, hipStream_t s) {
     const int64_t total = (int64_t)rows_st * ld;
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + CTA_WG - 1) / CTA_WG, 4096));
+    ProfScope ps("pad_matrix", s);
 #define CTA_PAD(TI, TO, A, B)                                                                 \
     if (tin == A && tout == B) {                                                              \
         k_pad_matrix<TI, TO><<<g, CTA_WG, 0, s>>>((const TI*)src, rows, cols, trans, (TO*)dst, \

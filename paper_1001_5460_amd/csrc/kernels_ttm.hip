@@ -3,6 +3,7 @@
 #include <algorithm>
 
 #include "launch.hpp"
+#include "prof.hpp"
 #include "reduce.hpp"
 #include "ttm.hpp"
 
@@ -69,6 +70,7 @@ hipError_t launch_strided(int tc, const void* X, void* Y, const Mat& M, int64_t 
     a.K = K; a.J = J; a.kpad = (K + dt_kstep(tc) - 1) / dt_kstep(tc) * dt_kstep(tc);
     a.lead = lead; a.trail = trail;
     if (a.kpad > M.ld) return hipErrorInvalidValue;
+    ProfScope ps(tc == DT_F64 ? "strided.f64" : tc == DT_F32 ? "strided.f32" : "strided.bf16", s);
     switch (tc) {
         case DT_F64: return strided_T<double, double, double>(a, done, s);
         case DT_F32: return strided_T<float, float, float>(a, done, s);
@@ -150,6 +152,7 @@ hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q
     a.K = K; a.J = J; a.kpad = (K + dt_kstep(tc) - 1) / dt_kstep(tc) * dt_kstep(tc);
     a.lead = 1; a.trail = trail;
     if (a.kpad > M.ld || K != J) return hipErrorInvalidValue;
+    ProfScope ps(tc == DT_F64 ? "normal_last.f64" : tc == DT_F32 ? "normal_last.f32" : "normal_last.bf16", s);
     if (tmid == DT_BF16 && tvec == DT_F32 && tc == DT_BF16)
         return last_T<bf16, float, bf16>(a, st, partials, scal, post, dot_out, done, s);
     if (tmid == DT_F32 && tvec == DT_F32 && tc == DT_F32)
@@ -219,6 +222,8 @@ hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const 
     if (a.k1pad > M1.ld || a.k2pad > M2.ld) return hipErrorInvalidValue;
     const size_t lds = tail_lds(tc, K1, J2);
     const bool fuse = Pvec != nullptr;
+    ProfScope ps(fuse ? (tc == DT_F64 ? "tail_p.f64" : tc == DT_F32 ? "tail_p.f32" : "tail_p.bf16")
+                      : (tc == DT_F64 ? "tail.f64" : tc == DT_F32 ? "tail.f32" : "tail.bf16"), s);
     if (tin == DT_F32 && tout == DT_BF16 && tc == DT_BF16)
         return fuse ? tail_T<float, bf16, bf16, true>(a, lds, s)
                     : tail_T<float, bf16, bf16, false>(a, lds, s);
@@ -275,6 +280,7 @@ hipError_t launch_contig(int tc, const void* X, void* Y, const Mat& M, int64_t r
     a.K = K; a.J = J; a.kpad = (K + dt_kstep(tc) - 1) / dt_kstep(tc) * dt_kstep(tc);
     a.rows = rows;
     if (a.kpad > M.ld) return hipErrorInvalidValue;
+    ProfScope ps(tc == DT_F64 ? "contig.f64" : tc == DT_F32 ? "contig.f32" : "contig.bf16", s);
     switch (tc) {
         case DT_F64: return contig_T<double>(a, done, s);
         case DT_F32: return contig_T<float>(a, done, s);

@@ -1,0 +1,113 @@
+// Kernel timing tracer (see prof.hpp) and its C ABI.
+#include "prof.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cta.h"
+#include "abi_internal.hpp"
+
+namespace cta {
+
+namespace {
+struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t take() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+bool prof_enabled() { return g_on; }
+
+int prof_begin(const char* name, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Rec r{name, take(), take()};
+    if (!r.a || !r.b) return -1;
+    if (hipEventRecord(r.a, s) != hipSuccess) return -1;
+    g_recs.push_back(r);
+    return (int)g_recs.size() - 1;
+}
+
+void prof_end(int id, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (id >= 0 && id < (int)g_recs.size()) (void)hipEventRecord(g_recs[id].b, s);
+}
+
+}  // namespace cta
+
+using namespace cta;
+
+extern "C" cta_status cta_prof_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_on = on != 0;
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_prof_reset(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (Rec& r : g_recs) {
+        (void)hipEventSynchronize(r.b);
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_prof_read(char* host_buf, size_t bytes, size_t* needed) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    struct Agg {
+        long count = 0;
+        double total_ms = 0, min_ms = 1e300, max_ms = 0;
+    };
+    std::map<std::string, Agg> agg;
+    for (Rec& r : g_recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(CTA_ERR_HIP, "event synchronize failed");
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(CTA_ERR_HIP, "event timing failed");
+        Agg& g = agg[r.name];
+        g.count += 1;
+        g.total_ms += ms;
+        g.min_ms = std::min(g.min_ms, (double)ms);
+        g.max_ms = std::max(g.max_ms, (double)ms);
+    }
+    std::string out = "{";
+    bool first = true;
+    for (auto& kv : agg) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s\"%s\": {\"count\": %ld, \"total_ms\": %.6f, \"min_ms\": %.6f, \"max_ms\": %.6f}",
+                 first ? "" : ", ", kv.first.c_str(), kv.second.count, kv.second.total_ms,
+                 kv.second.min_ms, kv.second.max_ms);
+        out += buf;
+        first = false;
+    }
+    out += "}";
+    if (needed) *needed = out.size();
+    if (host_buf && bytes > 0) {
+        const size_t n = std::min(bytes - 1, out.size());
+        std::memcpy(host_buf, out.data(), n);
+        host_buf[n] = 0;
+    }
+    return CTA_OK;
+}
