@@ -586,6 +586,10 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
             CTA_TRY(true_residual(op, B, X, tv, s, &rel_true));
             rel_true = bn2 > 0 ? rel_true / std::sqrt(bn2) : rel_true;
         }
+        // the recursive test passed but the recomputed residual is still above
+        // the tolerance after the restart: report it as not converged
+        if (done == DONE_CONVERGED && std::isfinite(rel_true) && rel_true > opts->rtol)
+            done = DONE_MAXITER;
         info->iters = total;
         info->refine_steps = 0;
         info->rel_res_recursive = rel_rec;

@@ -121,12 +121,50 @@ hipError_t launch_axpby(int tv, double a, const void* x, double b, void* y, int6
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ finalize
+// One workgroup: total = sum of partials in index order, then the scalar step.
+__global__ __launch_bounds__(CTA_WG) void k_finalize(const double* __restrict__ partials, int n,
+                                                     CgScalars* scal, int post, double* out) {
+    if ((post == POST_ALPHA || post == POST_RHO) && scal->done) return;
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += CTA_WG) acc += partials[i];
+    const double total = block_sum(acc, red);
+    if (threadIdx.x != 0) return;
+    if (post == POST_DOT) {
+        *out = total;
+    } else if (post == POST_ALPHA) {
+        scal->pq = total;
+        if (!(total > 0.0) || !__builtin_isfinite(total))
+            scal->done = DONE_BREAKDOWN;
+        else
+            scal->alpha = scal->rho / total;
+    } else if (post == POST_RHO) {
+        const double rho = scal->rho;
+        scal->beta = total / rho;
+        scal->rho = total;
+        scal->iters += 1;
+        if (!__builtin_isfinite(total))
+            scal->done = DONE_BREAKDOWN;
+        else if (total <= scal->threshold)
+            scal->done = DONE_CONVERGED;
+        else if (scal->iters >= scal->max_iter)
+            scal->done = DONE_MAXITER;
+    }
+}
+
+hipError_t launch_finalize(const double* partials, int n, CgScalars* scal, int post, double* out,
+                           hipStream_t s) {
+    ProfScope ps("finalize", s);
+    k_finalize<<<1, CTA_WG, 0, s>>>(partials, n, scal, post, out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ residual r = B - Q, <r, r>
 template <typename Tb, typename Tr>
 __global__ __launch_bounds__(CTA_WG) void k_residual(const Tb* __restrict__ B,
                                                      const Tb* __restrict__ Q, Tr* __restrict__ r,
-                                                     int64_t n, double* partials,
-                                                     unsigned* counter, double* out) {
+                                                     int64_t n, double* partials) {
     __shared__ double red[4];
     double acc = 0.0;
     CTA_SWEEP(n,
@@ -142,34 +180,35 @@ __global__ __launch_bounds__(CTA_WG) void k_residual(const Tb* __restrict__ B,
                   r[e] = v;
                   acc += (double)v * (double)v;
               })
-    double total;
-    if (grid_reduce(acc, partials, counter, red, total) && threadIdx.x == 0) *out = total;
+    block_partial(acc, partials, red);
 }
 
 hipError_t launch_residual(int tb, int tr, const void* B, const void* Q, void* r, int64_t n,
                            double* partials, CgScalars* scal, double* out, hipStream_t s) {
     const int g = red_grid(n);
-    unsigned* c = &scal->counter[1];
-    ProfScope ps(tb == DT_F64 ? (tr == DT_F64 ? "residual.f64" : "residual.f64_f32") : "residual.f32", s);
-    if (tb == DT_F64 && tr == DT_F64)
-        k_residual<double, double><<<g, CTA_WG, 0, s>>>((const double*)B, (const double*)Q,
-                                                        (double*)r, n, partials, c, out);
-    else if (tb == DT_F64 && tr == DT_F32)
-        k_residual<double, float><<<g, CTA_WG, 0, s>>>((const double*)B, (const double*)Q,
-                                                       (float*)r, n, partials, c, out);
-    else if (tb == DT_F32 && tr == DT_F32)
-        k_residual<float, float><<<g, CTA_WG, 0, s>>>((const float*)B, (const float*)Q,
-                                                      (float*)r, n, partials, c, out);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    {
+        ProfScope ps(tb == DT_F64 ? (tr == DT_F64 ? "residual.f64" : "residual.f64_f32") : "residual.f32", s);
+        if (tb == DT_F64 && tr == DT_F64)
+            k_residual<double, double><<<g, CTA_WG, 0, s>>>((const double*)B, (const double*)Q,
+                                                            (double*)r, n, partials);
+        else if (tb == DT_F64 && tr == DT_F32)
+            k_residual<double, float><<<g, CTA_WG, 0, s>>>((const double*)B, (const double*)Q,
+                                                           (float*)r, n, partials);
+        else if (tb == DT_F32 && tr == DT_F32)
+            k_residual<float, float><<<g, CTA_WG, 0, s>>>((const float*)B, (const float*)Q,
+                                                          (float*)r, n, partials);
+        else
+            return hipErrorInvalidValue;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_finalize(partials, g, scal, POST_DOT, out, s);
 }
 
 // ------------------------------------------------------------------ dot
 template <typename T>
 __global__ __launch_bounds__(CTA_WG) void k_dot(const T* __restrict__ x, const T* __restrict__ y,
-                                                int64_t n, double* partials, unsigned* counter,
-                                                double* out) {
+                                                int64_t n, double* partials) {
     __shared__ double red[4];
     double acc = 0.0;
     CTA_SWEEP(n,
@@ -177,32 +216,35 @@ __global__ __launch_bounds__(CTA_WG) void k_dot(const T* __restrict__ x, const T
                   for (int u = 0; u < kItems; ++u) acc += (double)x[i + u] * (double)y[i + u];
               },
               { acc += (double)x[e] * (double)y[e]; })
-    double total;
-    if (grid_reduce(acc, partials, counter, red, total) && threadIdx.x == 0) *out = total;
+    block_partial(acc, partials, red);
 }
 
 hipError_t launch_dot(int tv, const void* x, const void* y, int64_t n, double* partials,
                       CgScalars* scal, double* out, hipStream_t s) {
     const int g = red_grid(n);
-    unsigned* c = &scal->counter[2];
-    ProfScope ps(tv == DT_F64 ? "dot.f64" : "dot.f32", s);
-    if (tv == DT_F64)
-        k_dot<double><<<g, CTA_WG, 0, s>>>((const double*)x, (const double*)y, n, partials, c, out);
-    else if (tv == DT_F32)
-        k_dot<float><<<g, CTA_WG, 0, s>>>((const float*)x, (const float*)y, n, partials, c, out);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    {
+        ProfScope ps(tv == DT_F64 ? "dot.f64" : "dot.f32", s);
+        if (tv == DT_F64)
+            k_dot<double><<<g, CTA_WG, 0, s>>>((const double*)x, (const double*)y, n, partials);
+        else if (tv == DT_F32)
+            k_dot<float><<<g, CTA_WG, 0, s>>>((const float*)x, (const float*)y, n, partials);
+        else
+            return hipErrorInvalidValue;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_finalize(partials, g, scal, POST_DOT, out, s);
 }
 
 // ------------------------------------------------------------------ CG step
-// C += alpha P; R -= alpha Q; rho1 = <R, R>; P's update (P = R + beta P) is
-// fused into the first pass of the next operator application.
+// C += alpha P; R -= alpha Q; partial of rho1 = <R, R>.  The finalize kernel
+// forms beta and the convergence test; P = R + beta P is fused into the first
+// pass of the next operator application.
 template <typename T>
 __global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
                                                       const T* __restrict__ p,
                                                       const T* __restrict__ q, int64_t n,
-                                                      double* partials, CgScalars* scal) {
+                                                      double* partials, const CgScalars* scal) {
     if (scal->done) return;
     __shared__ double red[4];
     typedef typename V4<T>::type v4;
@@ -226,34 +268,26 @@ __global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __re
                   r[e] = rv;
                   acc += (double)rv * (double)rv;
               })
-    double rho1;
-    if (grid_reduce(acc, partials, &scal->counter[3], red, rho1) && threadIdx.x == 0) {
-        const double rho = scal->rho;
-        scal->beta = rho1 / rho;
-        scal->rho = rho1;
-        scal->iters += 1;
-        if (!__builtin_isfinite(rho1))
-            scal->done = DONE_BREAKDOWN;
-        else if (rho1 <= scal->threshold)
-            scal->done = DONE_CONVERGED;
-        else if (scal->iters >= scal->max_iter)
-            scal->done = DONE_MAXITER;
-    }
+    block_partial(acc, partials, red);
 }
 
 hipError_t launch_cg_update(int tv, void* x, void* r, const void* p, const void* q, int64_t n,
                             double* partials, CgScalars* scal, hipStream_t s) {
     const int g = red_grid(n);
-    ProfScope ps(tv == DT_F64 ? "cg_update.f64" : "cg_update.f32", s);
-    if (tv == DT_F64)
-        k_cg_update<double><<<g, CTA_WG, 0, s>>>((double*)x, (double*)r, (const double*)p,
-                                                 (const double*)q, n, partials, scal);
-    else if (tv == DT_F32)
-        k_cg_update<float><<<g, CTA_WG, 0, s>>>((float*)x, (float*)r, (const float*)p,
-                                                (const float*)q, n, partials, scal);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    {
+        ProfScope ps(tv == DT_F64 ? "cg_update.f64" : "cg_update.f32", s);
+        if (tv == DT_F64)
+            k_cg_update<double><<<g, CTA_WG, 0, s>>>((double*)x, (double*)r, (const double*)p,
+                                                     (const double*)q, n, partials, scal);
+        else if (tv == DT_F32)
+            k_cg_update<float><<<g, CTA_WG, 0, s>>>((float*)x, (float*)r, (const float*)p,
+                                                    (const float*)q, n, partials, scal);
+        else
+            return hipErrorInvalidValue;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_finalize(partials, g, scal, POST_RHO, nullptr, s);
 }
 
 __global__ void k_cg_setup(CgScalars* scal, double rtol2, int max_iter) {

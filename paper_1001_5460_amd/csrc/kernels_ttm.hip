@@ -80,48 +80,54 @@ hipError_t launch_strided(int tc, const void* X, void* Y, const Mat& M, int64_t 
 }
 
 // ------------------------------------------------------------------ normal-operator last pass
-template <typename Tmid, typename Tvec, typename Tc, int JT, int WJ, int CT>
+// Windowed epilogue (normal_last_tile) when its LDS fits, otherwise the
+// epilogue that reads every stencil point from memory (strided_tile<EPI>).
+template <typename Tmid, typename Tvec, typename Tc, int JT, int WJ, int CT, bool WINDOW>
 __global__ __launch_bounds__(CTA_WG) void k_normal_last(StridedArgs a, StencilArgs<Tvec> st,
-                                                        CgScalars* scal, int post, double* dot_out,
                                                         const int* done) {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4];
-    Tc* Xs = reinterpret_cast<Tc*>(smem);
     double dot = 0.0;
-    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
-        strided_tile<Tmid, Tvec, Tc, JT, WJ, CT, true>(a, tile, Xs, &st, dot);
-    double total = 0.0;
-    if (grid_reduce(dot, st.partials, &scal->counter[0], red, total) && threadIdx.x == 0) {
-        if (post == POST_DOT) {
-            *dot_out = total;
-        } else if (post == POST_ALPHA) {
-            scal->pq = total;
-            if (!(total > 0.0) || !__builtin_isfinite(total))
-                scal->done = DONE_BREAKDOWN;
-            else
-                scal->alpha = scal->rho / total;
-        }
+    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        if constexpr (WINDOW)
+            normal_last_tile<Tmid, Tvec, Tc, JT, WJ, CT>(a, tile, smem, st, dot);
+        else
+            strided_tile<Tmid, Tvec, Tc, JT, WJ, CT, true>(a, tile, reinterpret_cast<Tc*>(smem), &st, dot);
     }
+    block_partial(dot, st.partials, red);
 }
 
 template <typename Tmid, typename Tvec, typename Tc, int JT, int WJ, int CT>
-static hipError_t go_last(StridedArgs a, const StencilArgs<Tvec>& st, CgScalars* scal, int post,
-                          double* dot_out, const int* done, hipStream_t s) {
+static hipError_t go_last(StridedArgs a, const StencilArgs<Tvec>& st, int* grid_out,
+                          const int* done, hipStream_t s) {
     constexpr int TN = 16 * CT * (CTA_WAVES / WJ);
     a.ntt = (a.trail + TN - 1) / TN;
     a.ntiles = a.lead * a.ntt;
-    const size_t lds = (size_t)TN * (a.kpad + 16 / sizeof(Tc)) * sizeof(Tc);
-    auto kern = k_normal_last<Tmid, Tvec, Tc, JT, WJ, CT>;
-    hipError_t e = ensure_lds(kern, lds);
-    if (e != hipSuccess) return e;
-    kern<<<grid_for(a.ntiles, kMaxGrid), CTA_WG, lds, s>>>(a, st, scal, post, dot_out, done);
+    const size_t xs = (size_t)TN * (a.kpad + 16 / sizeof(Tc)) * sizeof(Tc);
+    const int nN = (int)st.ext[st.order - 1];
+    const size_t win = normal_last_lds<Tvec, Tc, TN>(a.kpad, a.K, a.J, nN);
+    const bool window = win <= 160 * 1024 && a.trail < (int64_t(1) << 30);
+    const int grid = grid_for(a.ntiles, kMaxGrid);
+    *grid_out = grid;
+    hipError_t e;
+    if (window) {
+        auto kern = k_normal_last<Tmid, Tvec, Tc, JT, WJ, CT, true>;
+        e = ensure_lds(kern, win);
+        if (e != hipSuccess) return e;
+        kern<<<grid, CTA_WG, win, s>>>(a, st, done);
+    } else {
+        auto kern = k_normal_last<Tmid, Tvec, Tc, JT, WJ, CT, false>;
+        e = ensure_lds(kern, xs);
+        if (e != hipSuccess) return e;
+        kern<<<grid, CTA_WG, xs, s>>>(a, st, done);
+    }
     return hipGetLastError();
 }
 
 template <typename Tmid, typename Tvec, typename Tc>
-static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, CgScalars* scal,
-                         int post, double* dot_out, const int* done, hipStream_t s) {
+static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, int* grid,
+                         const int* done, hipStream_t s) {
     StencilArgs<Tvec> st{};
     st.P = reinterpret_cast<const Tvec*>(d.P);
     for (int k = 0; k < 8; ++k) {
@@ -133,13 +139,13 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
     st.lam = d.lam;
     st.partials = partials;
     const int jt = (a.J + 15) / 16;
-    if (jt <= 1) return go_last<Tmid, Tvec, Tc, 1, 1, 1>(a, st, scal, post, dot_out, done, s);
-    if (jt <= 2) return go_last<Tmid, Tvec, Tc, 1, 2, 2>(a, st, scal, post, dot_out, done, s);
-    if (jt <= 4) return go_last<Tmid, Tvec, Tc, 1, 4, 4>(a, st, scal, post, dot_out, done, s);
-    if (jt <= 6) return go_last<Tmid, Tvec, Tc, 3, 2, 2>(a, st, scal, post, dot_out, done, s);
-    if (jt <= 8) return go_last<Tmid, Tvec, Tc, 2, 4, 4>(a, st, scal, post, dot_out, done, s);
-    if (jt <= 12) return go_last<Tmid, Tvec, Tc, 3, 4, 4>(a, st, scal, post, dot_out, done, s);
-    if (jt <= 16) return go_last<Tmid, Tvec, Tc, 4, 4, 4>(a, st, scal, post, dot_out, done, s);
+    if (jt <= 1) return go_last<Tmid, Tvec, Tc, 1, 1, 1>(a, st, grid, done, s);
+    if (jt <= 2) return go_last<Tmid, Tvec, Tc, 1, 2, 2>(a, st, grid, done, s);
+    if (jt <= 4) return go_last<Tmid, Tvec, Tc, 1, 4, 4>(a, st, grid, done, s);
+    if (jt <= 6) return go_last<Tmid, Tvec, Tc, 3, 2, 2>(a, st, grid, done, s);
+    if (jt <= 8) return go_last<Tmid, Tvec, Tc, 2, 4, 4>(a, st, grid, done, s);
+    if (jt <= 12) return go_last<Tmid, Tvec, Tc, 3, 4, 4>(a, st, grid, done, s);
+    if (jt <= 16) return go_last<Tmid, Tvec, Tc, 4, 4, 4>(a, st, grid, done, s);
     return hipErrorInvalidValue;
 }
 
@@ -152,14 +158,19 @@ hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q
     a.K = K; a.J = J; a.kpad = (K + dt_kstep(tc) - 1) / dt_kstep(tc) * dt_kstep(tc);
     a.lead = 1; a.trail = trail;
     if (a.kpad > M.ld || K != J) return hipErrorInvalidValue;
-    ProfScope ps(tc == DT_F64 ? "normal_last.f64" : tc == DT_F32 ? "normal_last.f32" : "normal_last.bf16", s);
-    if (tmid == DT_BF16 && tvec == DT_F32 && tc == DT_BF16)
-        return last_T<bf16, float, bf16>(a, st, partials, scal, post, dot_out, done, s);
-    if (tmid == DT_F32 && tvec == DT_F32 && tc == DT_F32)
-        return last_T<float, float, float>(a, st, partials, scal, post, dot_out, done, s);
-    if (tmid == DT_F64 && tvec == DT_F64 && tc == DT_F64)
-        return last_T<double, double, double>(a, st, partials, scal, post, dot_out, done, s);
-    return hipErrorInvalidValue;
+    int grid = 0;
+    hipError_t e = hipErrorInvalidValue;
+    {
+        ProfScope ps(tc == DT_F64 ? "normal_last.f64" : tc == DT_F32 ? "normal_last.f32" : "normal_last.bf16", s);
+        if (tmid == DT_BF16 && tvec == DT_F32 && tc == DT_BF16)
+            e = last_T<bf16, float, bf16>(a, st, partials, &grid, done, s);
+        else if (tmid == DT_F32 && tvec == DT_F32 && tc == DT_F32)
+            e = last_T<float, float, float>(a, st, partials, &grid, done, s);
+        else if (tmid == DT_F64 && tvec == DT_F64 && tc == DT_F64)
+            e = last_T<double, double, double>(a, st, partials, &grid, done, s);
+    }
+    if (e != hipSuccess || post == POST_NONE) return e;
+    return launch_finalize(partials, grid, scal, post, dot_out, s);
 }
 
 // ------------------------------------------------------------------ tail
@@ -167,9 +178,12 @@ template <typename Tin, typename Tout, typename Tc, int J2T, bool FUSE_P>
 __global__ __launch_bounds__(CTA_WG) void k_tail(TailArgs a) {
     if (a.done && *a.done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    Tc* Zt = reinterpret_cast<Tc*>(smem);
-    for (int64_t blk = blockIdx.x; blk < a.nblk; blk += gridDim.x)
-        tail_block<Tin, Tout, Tc, J2T, FUSE_P>(a, blk, Zt);
+    const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int64_t blk0 = grp * a.nbg;
+        const int nb = (int)std::min<int64_t>(a.nbg, a.nblk - blk0);
+        tail_group<Tin, Tout, Tc, J2T, FUSE_P>(a, blk0, nb, a.nbg, smem);
+    }
 }
 
 // K1 is padded to the MFMA K step and to the 16-row tiles of the first step.
@@ -178,20 +192,30 @@ static int tail_k1pad(int tc, int K1) {
     return (K1 + g - 1) / g * g;
 }
 
-static size_t tail_lds(int tc, int K1, int J2) {
-    const int k1pad = tail_k1pad(tc, K1);
-    const int j2t = (J2 + 15) / 16;
-    return (size_t)j2t * 16 * (k1pad + 16 / dt_size(tc)) * dt_size(tc);
+static size_t tail_lds_nb(int tc, int tout, int K1, int J1, int J2, int nb) {
+    const size_t z = (size_t)nb * tail_zt_elems(tail_k1pad(tc, K1), J2, dt_size(tc)) * dt_size(tc);
+    return (z + 15) / 16 * 16 + (size_t)nb * J1 * J2 * dt_size(tout);
+}
+
+// Blocks per group: enough 16-row tiles to keep the four waves equally busy,
+// within a 64 KiB LDS budget.
+static int tail_nb(int tc, int tout, int K1, int J1, int J2) {
+    const int ni1t = tail_k1pad(tc, K1) / 16;
+    int nb = (ni1t % 4 == 0) ? 1 : (ni1t % 2 == 0 ? 2 : 4);
+    while (nb > 1 && tail_lds_nb(tc, tout, K1, J1, J2, nb) > 64 * 1024) nb /= 2;
+    return nb;
 }
 
 bool tail_fits(int tc, int K1, int J2) {
-    return J2 <= 256 && K1 <= 256 && tail_lds(tc, K1, J2) <= 64 * 1024;
+    // the output staging uses the widest output type of any caller (8 bytes)
+    return J2 <= 256 && K1 <= 256 && tail_lds_nb(tc, DT_F64, K1, K1, J2, 1) <= 160 * 1024;
 }
 
 template <typename Tin, typename Tout, typename Tc, bool FUSE_P>
 static hipError_t tail_T(const TailArgs& a, size_t lds, hipStream_t s) {
     const int j2t = (a.J2 + 15) / 16;
-    const int grid = grid_for(a.nblk, 65536);
+    const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
+    const int grid = grid_for(ngroups, 65536);
 #define CTA_TAIL_GO(N)                                                          \
     {                                                                           \
         auto kern = k_tail<Tin, Tout, Tc, N, FUSE_P>;                           \
@@ -211,7 +235,7 @@ static hipError_t tail_T(const TailArgs& a, size_t lds, hipStream_t s) {
 hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const Mat& M1,
                        const Mat& M2, int64_t nblk, int K1, int K2, int J1, int J2, void* Pvec,
                        const double* beta, const int* done, hipStream_t s) {
-    if (!tail_fits(tc, K1, J2)) return hipErrorInvalidValue;
+    if (!tail_fits(tc, K1, J2) || J1 > 256) return hipErrorInvalidValue;
     const int ks = dt_kstep(tc);
     TailArgs a{};
     a.X = X; a.Y = Y; a.M1 = M1.p; a.M2 = M2.p; a.ldm1 = M1.ld; a.ldm2 = M2.ld;
@@ -219,8 +243,10 @@ hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const 
     a.k1pad = tail_k1pad(tc, K1);
     a.k2pad = (K2 + ks - 1) / ks * ks;
     a.nblk = nblk; a.Pvec = Pvec; a.beta = beta; a.done = done;
+    a.nbg = tail_nb(tc, tout, K1, J1, J2);
     if (a.k1pad > M1.ld || a.k2pad > M2.ld) return hipErrorInvalidValue;
-    const size_t lds = tail_lds(tc, K1, J2);
+    const size_t lds = tail_lds_nb(tc, tout, K1, J1, J2, a.nbg);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     const bool fuse = Pvec != nullptr;
     ProfScope ps(fuse ? (tc == DT_F64 ? "tail_p.f64" : tc == DT_F32 ? "tail_p.f32" : "tail_p.bf16")
                       : (tc == DT_F64 ? "tail.f64" : tc == DT_F32 ? "tail.f32" : "tail.bf16"), s);

@@ -33,7 +33,8 @@ struct CgScalars {
     int done;          // 0 running, 1 converged, 2 breakdown, 3 iteration limit
     int max_iter;
     int pad0;
-    unsigned counter[4];  // arrival counters of grid reductions (kept at zero between launches)
+    int nblk;          // number of partials written by the last reduction kernel
+    int pad1;
 };
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_BREAKDOWN = 2, DONE_MAXITER = 3 };
@@ -48,11 +49,20 @@ struct StencilDesc {
     double lam;
 };
 
-// Post-processing done by the last workgroup of the normal-operator pass.
-enum { POST_NONE = 0, POST_DOT = 1, POST_ALPHA = 2 };
+// What the finalize kernel does with the reduced total.
+enum {
+    POST_NONE = 0,   // nothing
+    POST_DOT = 1,    // *out = total
+    POST_ALPHA = 2,  // pq = total; alpha = rho / pq (breakdown if pq <= 0)
+    POST_RHO = 3     // rho1 = total; beta = rho1 / rho; rho = rho1; iters++; convergence test
+};
 
-// Maximum grid of the tile-loop kernels (and size of the partials array).
-constexpr int kMaxGrid = 4096;
+// Maximum grid of the reducing kernels (and size of the partials array).
+constexpr int kMaxGrid = 16384;
+
+// Sum partials[0..n) in index order and apply `post` (one workgroup).
+hipError_t launch_finalize(const double* partials, int n, CgScalars* scal, int post, double* out,
+                           hipStream_t s);
 
 // ---- TTM passes ----
 hipError_t launch_strided(int tc, const void* X, void* Y, const Mat& M, int64_t lead, int K, int J,

@@ -48,6 +48,7 @@ struct StridedArgs {
 };
 
 struct TailArgs {
+    int nbg;         // blocks per workgroup group
     const void* X;   // (nblk, K1, K2)  (or r when fused with the p update)
     void* Y;         // (nblk, J1, J2)
     const void* M1;  // Tc [>= J1 pad][ldm1]
@@ -213,18 +214,276 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int64_t tile,
 }
 
 // ---------------------------------------------------------------------------
-// Tail pass on blocks of the last two modes.  J2T: maximum number of 16-wide
-// j2 tiles (compile time), the runtime count is (J2 + 15) / 16.
+// Normal-operator last pass (mode 1 of a (K, trail) tensor, lead == 1):
+//   Q[j, t] = sum_i M[j, i] X[i, t] + lam * sum_k (P x_k R_k)[j, t],  dot += P Q.
+// LDS holds the transposed X tile (MFMA operand), then -- reusing that space --
+// the MFMA result Qs[j][c]; beside it a window of P (all K rows, TN + 8
+// columns with 4 columns of halo per side) and the band rows of R_1 and R_N.
+// The epilogue runs one item per thread per iteration: E = 16 / sizeof(Tv)
+// consecutive columns of one row, so global loads and stores are 16-byte
+// vectors and consecutive threads touch consecutive memory.  Modes 1 and N
+// of the regulariser read the window; the modes in between (strides of whole
+// mode-N rows) read P from memory.  Index arithmetic is 32-bit (the launcher
+// checks trail < 2^30).
+template <typename Tv>
+struct LastLds {
+    static constexpr int H = 4;  // halo columns per side
+};
+
+template <typename Tin, typename Tv, typename Tc, int JT, int WJ, int CT>
+__device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t tile,
+                                                 unsigned char* smem, const StencilArgs<Tv>& st,
+                                                 double& dot_acc) {
+    typedef MT<Tc> T;
+    constexpr int WC = CTA_WAVES / WJ;
+    constexpr int TN = 16 * CT * WC;
+    constexpr int VEC = T::VEC;
+    constexpr int LV = 16 / sizeof(Tin);
+    constexpr int E = 16 / sizeof(Tv);      // epilogue item width (one 16-byte vector)
+    constexpr int H = LastLds<Tv>::H;
+    constexpr int LDP = TN + 2 * H;         // P window pitch
+    constexpr int LDQ = TN + E;             // Qs pitch
+    typedef Tv __attribute__((ext_vector_type(E))) vt;
+    const int ldx = a.kpad + 16 / (int)sizeof(Tc);
+    const int K = a.K;
+    const int trail = (int)a.trail;
+    const int t0 = (int)tile * TN;
+    const int N = st.order;
+    const int nN = (int)st.ext[N - 1];
+    const size_t xs_bytes = (size_t)TN * ldx * sizeof(Tc);
+    const size_t qs_bytes = (size_t)a.J * LDQ * sizeof(Tv);
+    const size_t a_bytes = (xs_bytes > qs_bytes ? xs_bytes : qs_bytes + 0);
+    Tc* Xs = reinterpret_cast<Tc*>(smem);
+    Tv* Qs = reinterpret_cast<Tv*>(smem);
+    Tv* Pw = reinterpret_cast<Tv*>(smem + ((a_bytes + 15) / 16) * 16);
+    Tv* band1 = Pw + (size_t)K * LDP;
+    Tv* bandN = band1 + (size_t)K * 5;
+    const bool has1 = st.rband[0] != nullptr;
+    const bool hasN = st.rband[N - 1] != nullptr;
+    const Tin* __restrict__ X = reinterpret_cast<const Tin*>(a.X);
+    Tv* __restrict__ Q = reinterpret_cast<Tv*>(a.Y);
+    const Tv* __restrict__ P = st.P;
+    const Tc* __restrict__ M = reinterpret_cast<const Tc*>(a.M);
+
+    // ---- stage the X tile (transposed, Tc) ----
+    const bool vec_ok = (trail % LV) == 0;
+    {
+        constexpr int TCH = TN / LV;
+        const int nunits = (a.kpad / VEC) * TCH;
+        for (int u = threadIdx.x; u < nunits; u += CTA_WG) {
+            const int tc = u % TCH;
+            const int kg = u / TCH;
+            const int t = t0 + tc * LV;
+            Tin v[VEC][LV];
+#pragma unroll
+            for (int r = 0; r < VEC; ++r) {
+                const int k = kg * VEC + r;
+                if (k < K && vec_ok && t + LV <= trail) {
+                    typedef Tin __attribute__((ext_vector_type(LV))) vin;
+                    vin x = *reinterpret_cast<const vin*>(X + (int64_t)k * trail + t);
+#pragma unroll
+                    for (int c = 0; c < LV; ++c) v[r][c] = x[c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < LV; ++c)
+                        v[r][c] = (k < K && t + c < trail) ? X[(int64_t)k * trail + t + c] : cvt<Tin>(0.f);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < LV; ++c) {
+                typename T::frag f;
+#pragma unroll
+                for (int r = 0; r < VEC; ++r) f[r] = cvt<Tc>(v[r][c]);
+                *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
+            }
+        }
+    }
+    // ---- stage the P window and the band rows ----
+    const bool pvec = (trail % E) == 0;
+    {
+        constexpr int PCH = LDP / E;
+        for (int u = threadIdx.x; u < K * PCH; u += CTA_WG) {
+            const int row = u / PCH, ch = u % PCH;
+            const int t = t0 - H + ch * E;
+            const Tv* src = P + (int64_t)row * trail + t;
+            Tv* dst = Pw + row * LDP + ch * E;
+            if (pvec && t >= 0 && t + E <= trail) {
+                *reinterpret_cast<vt*>(dst) = *reinterpret_cast<const vt*>(src);
+            } else {
+#pragma unroll
+                for (int c = 0; c < E; ++c) dst[c] = (t + c >= 0 && t + c < trail) ? src[c] : Tv(0);
+            }
+        }
+        if (has1)
+            for (int u = threadIdx.x; u < K * 5; u += CTA_WG) band1[u] = st.rband[0][u];
+        if (hasN)
+            for (int u = threadIdx.x; u < nN * 5; u += CTA_WG) bandN[u] = st.rband[N - 1][u];
+    }
+    __syncthreads();
+
+    // ---- MFMA ----
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wj = wave % WJ, wc = wave / WJ;
+        const int cb = wc * CT * 16, jb = wj * JT * 16;
+        const int g = lane >> 4, l16 = lane & 15;
+        typename T::acc acc[JT][CT];
+#pragma unroll
+        for (int x = 0; x < JT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
+        const int nks = a.kpad / T::KSTEP;
+        for (int ks = 0; ks < nks; ++ks) {
+            const int k0 = ks * T::KSTEP + VEC * g;
+            typename T::frag xa[CT], mb[JT];
+#pragma unroll
+            for (int y = 0; y < CT; ++y)
+                xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (cb + y * 16 + l16) * ldx + k0);
+#pragma unroll
+            for (int x = 0; x < JT; ++x)
+                mb[x] = *reinterpret_cast<const typename T::frag*>(
+                    M + (int64_t)(jb + x * 16 + l16) * a.ldm + k0);
+#pragma unroll
+            for (int x = 0; x < JT; ++x)
+#pragma unroll
+                for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
+        }
+        __syncthreads();  // Xs is dead; its space becomes Qs
+#pragma unroll
+        for (int x = 0; x < JT; ++x) {
+            const int j = jb + x * 16 + l16;
+            if (j >= a.J) continue;
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+                if constexpr (T::CONSEC && E == 4) {
+                    vt o;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) o[r] = cvt<Tv>(acc[x][y][r]);
+                    *reinterpret_cast<vt*>(Qs + j * LDQ + cb + y * 16 + 4 * g) = o;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Qs[j * LDQ + cb + y * 16 + T::arow(lane, r)] = cvt<Tv>(acc[x][y][r]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- epilogue: one item = E consecutive columns of one row ----
+    const Tv lam = (Tv)st.lam;
+    const bool fast = pvec && (nN % E) == 0;
+    constexpr int GPR = TN / E;  // items per row
+    for (int it = threadIdx.x; it < a.J * GPR; it += CTA_WG) {
+        const int j = it / GPR;
+        const int c = (it - j * GPR) * E;
+        const int t = t0 + c;
+        if (t >= trail) continue;
+        const Tv* prow = Pw + j * LDP + H + c;  // prow[0] is P[j][t]
+        const int64_t base = (int64_t)j * trail + t;
+        if (fast) {
+            const vt pc = *reinterpret_cast<const vt*>(prow);
+            vt s;
+#pragma unroll
+            for (int e = 0; e < E; ++e) s[e] = Tv(0);
+            if (has1) {
+#pragma unroll
+                for (int d = -2; d <= 2; ++d)
+                    if (j + d >= 0 && j + d < K)
+                        s += band1[j * 5 + d + 2] * *reinterpret_cast<const vt*>(prow + d * LDP);
+            }
+            if (hasN) {
+                Tv w[3 * E];
+                const vt pl = *reinterpret_cast<const vt*>(prow - E);
+                const vt pr = *reinterpret_cast<const vt*>(prow + E);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    w[e] = pl[e];
+                    w[E + e] = pc[e];
+                    w[2 * E + e] = pr[e];
+                }
+                const int i0 = t % nN;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int iN = i0 + e;
+                    const Tv* bN = bandN + iN * 5;
+#pragma unroll
+                    for (int d = -2; d <= 2; ++d)
+                        if (iN + d >= 0 && iN + d < nN) s[e] += bN[d + 2] * w[E + e + d];
+                }
+            }
+            for (int k = 1; k < N - 1; ++k) {
+                const Tv* __restrict__ rb = st.rband[k];
+                if (!rb) continue;
+                const int sk = (int)st.stride[k], nk = (int)st.ext[k];
+                const int ik = (t / sk) % nk;
+                const Tv* br = rb + ik * 5;
+                s += br[2] * pc;
+#pragma unroll
+                for (int d = -2; d <= 2; ++d)
+                    if (d != 0 && ik + d >= 0 && ik + d < nk)
+                        s += br[d + 2] * *reinterpret_cast<const vt*>(P + base + (int64_t)d * sk);
+            }
+            const vt qv = *reinterpret_cast<const vt*>(Qs + j * LDQ + c) + lam * s;
+            *reinterpret_cast<vt*>(Q + base) = qv;
+#pragma unroll
+            for (int e = 0; e < E; ++e) dot_acc += (double)pc[e] * (double)qv[e];
+        } else {
+            for (int e = 0; e < E && t + e < trail; ++e) {
+                const int te = t + e;
+                const int64_t be = base + e;
+                Tv sv = Tv(0);
+                for (int k = 0; k < N; ++k) {
+                    const Tv* __restrict__ rb = st.rband[k];
+                    if (!rb) continue;
+                    const int sk = (int)st.stride[k], nk = (int)st.ext[k];
+                    const int ik = (k == 0) ? j : (te / sk) % nk;
+                    const Tv* br = rb + ik * 5;
+                    for (int d = -2; d <= 2; ++d)
+                        if (ik + d >= 0 && ik + d < nk) sv += br[d + 2] * P[be + (int64_t)d * sk];
+                }
+                const Tv pv = P[be];
+                const Tv qv = Qs[j * LDQ + c + e] + lam * sv;
+                Q[be] = qv;
+                dot_acc += (double)pv * (double)qv;
+            }
+        }
+    }
+    __syncthreads();  // LDS is reused by the next tile
+}
+
+// LDS bytes of normal_last_tile.
+template <typename Tv, typename Tc, int TN>
+inline size_t normal_last_lds(int kpad, int K, int J, int nN) {
+    const size_t xs = (size_t)TN * (kpad + 16 / sizeof(Tc)) * sizeof(Tc);
+    const size_t qs = (size_t)J * (TN + 16 / sizeof(Tv)) * sizeof(Tv);
+    const size_t a = ((xs > qs ? xs : qs) + 15) / 16 * 16;
+    return a + (size_t)K * (TN + 2 * LastLds<Tv>::H) * sizeof(Tv) + (size_t)(K + nN) * 5 * sizeof(Tv);
+}
+
+// ---------------------------------------------------------------------------
+// Tail pass on groups of `nb` consecutive blocks of the last two modes.  J2T:
+// maximum number of 16-wide j2 tiles (compile time); the runtime count is
+// (J2 + 15) / 16.  LDS: Zt for every block of the group, then the output
+// blocks Ys, which are written back as one contiguous run (consecutive blocks
+// are adjacent in memory).
+__host__ __device__ inline int tail_zt_elems(int k1pad, int J2, int tc_size) {
+    return ((J2 + 15) / 16) * 16 * (k1pad + 16 / tc_size);
+}
+
 template <typename Tin, typename Tout, typename Tc, int J2T, bool FUSE_P>
-__device__ __forceinline__ void tail_block(const TailArgs& a, int64_t blk, Tc* Zt) {
+__device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int nb, int nbmax,
+                                           unsigned char* smem) {
     typedef MT<Tc> T;
     constexpr int VEC = T::VEC;
     const int ldz = a.k1pad + 16 / (int)sizeof(Tc);
+    const int zsz = tail_zt_elems(a.k1pad, a.J2, (int)sizeof(Tc));
+    Tc* Zt = reinterpret_cast<Tc*>(smem);
+    Tout* Ys = reinterpret_cast<Tout*>(smem + (((size_t)nbmax * zsz * sizeof(Tc) + 15) / 16) * 16);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, l16 = lane & 15;
-    const int64_t in_off = blk * (int64_t)a.K1 * a.K2;
-    const Tin* __restrict__ X = reinterpret_cast<const Tin*>(a.X) + in_off;
-    Tin* __restrict__ Pv = FUSE_P ? reinterpret_cast<Tin*>(a.Pvec) + in_off : nullptr;
+    const int64_t bin = (int64_t)a.K1 * a.K2;
+    const int bout = a.J1 * a.J2;
     const Tc* __restrict__ M1 = reinterpret_cast<const Tc*>(a.M1);
     const Tc* __restrict__ M2 = reinterpret_cast<const Tc*>(a.M2);
     Tin beta = cvt<Tin>(0.f);
@@ -232,32 +491,49 @@ __device__ __forceinline__ void tail_block(const TailArgs& a, int64_t blk, Tc* Z
     const int nj2t = (a.J2 + 15) / 16;
     const int ni1t = a.k1pad / 16;
     const int nks2 = a.k2pad / T::KSTEP;
+    const bool aligned2 = (a.K2 % VEC) == 0;
 
-    // ---- step 1: Zt[j2][i1] = sum_k2 X[i1][k2] M2[j2][k2] ----
-    for (int it = wave; it < ni1t; it += CTA_WAVES) {
-        const int i1 = it * 16 + l16;
+    // ---- step 1: Zt[b][j2][i1] = sum_k2 X_b[i1][k2] M2[j2][k2] ----
+    for (int it = wave; it < nb * ni1t; it += CTA_WAVES) {
+        const int bl = it / ni1t, ti = it - bl * ni1t;
+        const int64_t off0 = (blk0 + bl) * bin;
+        const Tin* __restrict__ X = reinterpret_cast<const Tin*>(a.X) + off0;
+        const int i1 = ti * 16 + l16;
         typename T::acc acc[J2T];
 #pragma unroll
         for (int x = 0; x < J2T; ++x) acc[x] = T::zero();
         for (int ks = 0; ks < nks2; ++ks) {
             const int k2 = ks * T::KSTEP + VEC * g;
-            typename T::frag xf;
             const int nv = (i1 < a.K1) ? max(0, min(VEC, a.K2 - k2)) : 0;
+            typename T::frag xf = T::zfrag();
             if constexpr (FUSE_P) {
                 // p = r + beta * p on the fly; the new p is written back once
-                xf = T::zfrag();
+                Tin* __restrict__ Pv = reinterpret_cast<Tin*>(a.Pvec) + off0;
                 const int64_t off = (int64_t)i1 * a.K2 + k2;
+                constexpr int LV = 16 / sizeof(Tin);
+                if (nv == VEC && aligned2 && (VEC % LV) == 0) {
+                    typedef Tin __attribute__((ext_vector_type(LV))) vin;
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) {
-                    if (v < nv) {
-                        const Tin pn = X[off + v] + beta * Pv[off + v];
-                        Pv[off + v] = pn;
-                        xf[v] = cvt<Tc>(pn);
+                    for (int h = 0; h < VEC / LV; ++h) {
+                        const vin rv = *reinterpret_cast<const vin*>(X + off + h * LV);
+                        const vin pv = *reinterpret_cast<const vin*>(Pv + off + h * LV);
+                        const vin pn = rv + beta * pv;
+                        *reinterpret_cast<vin*>(Pv + off + h * LV) = pn;
+#pragma unroll
+                        for (int v = 0; v < LV; ++v) xf[h * LV + v] = cvt<Tc>(pn[v]);
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        if (v < nv) {
+                            const Tin pn = X[off + v] + beta * Pv[off + v];
+                            Pv[off + v] = pn;
+                            xf[v] = cvt<Tc>(pn);
+                        }
                     }
                 }
             } else {
-                xf = (nv > 0) ? load_frag<Tc>(X + (int64_t)i1 * a.K2 + k2, nv, (a.K2 % VEC) == 0)
-                               : T::zfrag();
+                if (nv > 0) xf = load_frag<Tc>(X + (int64_t)i1 * a.K2 + k2, nv, aligned2);
             }
 #pragma unroll
             for (int x = 0; x < J2T; ++x) {
@@ -268,61 +544,60 @@ __device__ __forceinline__ void tail_block(const TailArgs& a, int64_t blk, Tc* Z
                 }
             }
         }
-        // D[i1][j2]: lane owns i1 = it*16 + arow(lane, r), j2 = x*16 + l16
+        Tc* Zb = Zt + bl * zsz;
 #pragma unroll
         for (int x = 0; x < J2T; ++x) {
             if (x < nj2t) {
                 const int j2 = x * 16 + l16;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    Zt[j2 * ldz + it * 16 + T::arow(lane, r)] = cvt<Tc>(acc[x][r]);
+                    Zb[j2 * ldz + ti * 16 + T::arow(lane, r)] = cvt<Tc>(acc[x][r]);
             }
         }
     }
     __syncthreads();
 
-    // ---- step 2: Y[j1][j2] = sum_i1 M1[j1][i1] Zt[j2][i1]; D[j2][j1] ----
+    // ---- step 2: Ys[b][j1][j2] = sum_i1 M1[j1][i1] Zt[b][j2][i1] ----
     const int nj1t = (a.J1 + 15) / 16;
     const int nsub = nj2t * nj1t;
     const int nks1 = a.k1pad / T::KSTEP;
-    Tout* __restrict__ Y = reinterpret_cast<Tout*>(a.Y) + blk * (int64_t)a.J1 * a.J2;
-    for (int s = wave; s < nsub; s += CTA_WAVES) {
-        const int x2 = s % nj2t, x1 = s / nj2t;
+    for (int sidx = wave; sidx < nb * nsub; sidx += CTA_WAVES) {
+        const int bl = sidx / nsub, sb = sidx - bl * nsub;
+        const int x2 = sb % nj2t, x1 = sb / nj2t;
+        const Tc* Zb = Zt + bl * zsz;
         typename T::acc acc = T::zero();
         for (int ks = 0; ks < nks1; ++ks) {
             const int k1 = ks * T::KSTEP + VEC * g;
             const typename T::frag zf =
-                *reinterpret_cast<const typename T::frag*>(Zt + (x2 * 16 + l16) * ldz + k1);
+                *reinterpret_cast<const typename T::frag*>(Zb + (x2 * 16 + l16) * ldz + k1);
             const typename T::frag mf = *reinterpret_cast<const typename T::frag*>(
                 M1 + (int64_t)(x1 * 16 + l16) * a.ldm1 + k1);
             acc = T::mma(zf, mf, acc);
         }
         const int j1 = x1 * 16 + l16;
         if (j1 < a.J1) {
-            if constexpr (T::CONSEC) {
-                const int j2 = x2 * 16 + 4 * g;
-                Tout* dst = Y + (int64_t)j1 * a.J2 + j2;
-                if ((a.J2 % 4) == 0 && j2 + 4 <= a.J2) {
-                    typedef Tout __attribute__((ext_vector_type(4))) vout;
-                    vout o;
+            Tout* yb = Ys + bl * bout + j1 * a.J2;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) o[r] = cvt<Tout>(acc[r]);
-                    *reinterpret_cast<vout*>(dst) = o;
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (j2 + r < a.J2) dst[r] = cvt<Tout>(acc[r]);
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j2 = x2 * 16 + T::arow(lane, r);
-                    if (j2 < a.J2) Y[(int64_t)j1 * a.J2 + j2] = cvt<Tout>(acc[r]);
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int j2 = x2 * 16 + T::arow(lane, r);
+                if (j2 < a.J2) yb[j2] = cvt<Tout>(acc[r]);
             }
         }
     }
-    __syncthreads();  // Zt is reused by the next block
+    __syncthreads();
+
+    // ---- contiguous write-back of the nb output blocks ----
+    Tout* __restrict__ Y = reinterpret_cast<Tout*>(a.Y) + blk0 * bout;
+    const int total = nb * bout;
+    constexpr int OV = 16 / sizeof(Tout);
+    if ((reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (total % OV) == 0) {
+        typedef Tout __attribute__((ext_vector_type(OV))) vo;
+        for (int i = threadIdx.x * OV; i < total; i += CTA_WG * OV)
+            *reinterpret_cast<vo*>(Y + i) = *reinterpret_cast<const vo*>(Ys + i);
+    } else {
+        for (int i = threadIdx.x; i < total; i += CTA_WG) Y[i] = Ys[i];
+    }
+    __syncthreads();  // LDS is reused by the next group
 }
 
 // ---------------------------------------------------------------------------
