@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--max-inner", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the library's plain copy kernel (FP32, one 128x128x96x24 "
+                         "tensor, 5 launches) for counter calibration, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build solves on one GPU only; --gpus {args.gpus} is not supported "
@@ -138,6 +141,19 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     cta = ensure_library()
     import workload
+
+    if args.calibrate_copy:
+        n = workload.CONFIGS[2]["n"]
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        for _ in range(5):
+            # empty mode mask: the library casts X to its workspace and back (two
+            # FP32 -> FP32 copy launches of N elements each)
+            cta.cta_ttm(src, [None] * len(n), compute="f32")
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "elements": int(np.prod(n)),
+                          "bytes_read_per_launch": 4 * int(np.prod(n)),
+                          "bytes_written_per_launch": 4 * int(np.prod(n)), "launches": 10}))
+        return
 
     p = workload.config_problem(2)
     n = p.n

@@ -15,6 +15,15 @@ typedef __attribute__((ext_vector_type(4))) double doublex4;
 
 #define CTA_WG 256          // threads per workgroup (4 waves of 64)
 #define CTA_WAVES 4
+#define CTA_XCDS 8          // MI355X: workgroups are dealt round-robin to 8 XCDs
+
+// XCD-aware workgroup order.  Hardware deals workgroup b to XCD b % 8; this
+// renumbering gives XCD x the contiguous range [x*G/8, (x+1)*G/8) of logical
+// ids (in dispatch order), so tiles that are neighbours in memory run on the
+// same XCD and share its L2.  G must be a multiple of 8.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t G) {
+    return (b % CTA_XCDS) * (G / CTA_XCDS) + b / CTA_XCDS;
+}
 
 // ---------------------------------------------------------------------------
 // Conversions (float -> bf16 rounds to nearest even on gfx950).

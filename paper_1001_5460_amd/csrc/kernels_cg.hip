@@ -123,14 +123,28 @@ hipError_t launch_axpby(int tv, double a, const void* x, double b, void* y, int6
 
 // ------------------------------------------------------------------ finalize
 // One workgroup: total = sum of partials in index order, then the scalar step.
-__global__ __launch_bounds__(CTA_WG) void k_finalize(const double* __restrict__ partials, int n,
-                                                     CgScalars* scal, int post, double* out) {
+__global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ partials, int n,
+                                                   CgScalars* scal, int post, double* out) {
     if ((post == POST_ALPHA || post == POST_RHO) && scal->done) return;
-    __shared__ double red[4];
+    __shared__ double red[16];
+    // thread i sums partials i, i+1024, i+2048, ... (loads issued four at a time)
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += CTA_WG) acc += partials[i];
-    const double total = block_sum(acc, red);
+    int i = threadIdx.x;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+        const double a0 = partials[i], a1 = partials[i + 1024];
+        const double a2 = partials[i + 2048], a3 = partials[i + 3072];
+        acc += a0;
+        acc += a1;
+        acc += a2;
+        acc += a3;
+    }
+    for (; i < n; i += 1024) acc += partials[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    double total = 0.0;
+    for (int w = 0; w < 16; ++w) total += red[w];
     if (post == POST_DOT) {
         *out = total;
     } else if (post == POST_ALPHA) {
@@ -156,7 +170,7 @@ __global__ __launch_bounds__(CTA_WG) void k_finalize(const double* __restrict__ 
 hipError_t launch_finalize(const double* partials, int n, CgScalars* scal, int post, double* out,
                            hipStream_t s) {
     ProfScope ps("finalize", s);
-    k_finalize<<<1, CTA_WG, 0, s>>>(partials, n, scal, post, out);
+    k_finalize<<<1, 1024, 0, s>>>(partials, n, scal, post, out);
     return hipGetLastError();
 }
 

@@ -89,7 +89,8 @@ __global__ __launch_bounds__(CTA_WG) void k_normal_last(StridedArgs a, StencilAr
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4];
     double dot = 0.0;
-    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    for (int64_t tile = lb; tile < a.ntiles; tile += gridDim.x) {
         if constexpr (WINDOW)
             normal_last_tile<Tmid, Tvec, Tc, JT, WJ, CT>(a, tile, smem, st, dot);
         else
@@ -108,7 +109,8 @@ static hipError_t go_last(StridedArgs a, const StencilArgs<Tvec>& st, int* grid_
     const int nN = (int)st.ext[st.order - 1];
     const size_t win = normal_last_lds<Tvec, Tc, TN>(a.kpad, a.K, a.J, nN);
     const bool window = win <= 160 * 1024 && a.trail < (int64_t(1) << 30);
-    const int grid = grid_for(a.ntiles, kMaxGrid);
+    // a multiple of the XCD count, for the XCD-aware tile order
+    const int grid = (grid_for(a.ntiles, kMaxGrid) + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
     *grid_out = grid;
     hipError_t e;
     if (window) {

@@ -374,6 +374,7 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
     const Tv lam = (Tv)st.lam;
     const bool fast = pvec && (nN % E) == 0;
     constexpr int GPR = TN / E;  // items per row
+#pragma unroll 2
     for (int it = threadIdx.x; it < a.J * GPR; it += CTA_WG) {
         const int j = it / GPR;
         const int c = (it - j * GPR) * E;
@@ -382,15 +383,20 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
         const Tv* prow = Pw + j * LDP + H + c;  // prow[0] is P[j][t]
         const int64_t base = (int64_t)j * trail + t;
         if (fast) {
+            // Branch-free taps: a tap outside the tensor has a zero band
+            // coefficient (R_k[i][i+d] with i+d out of range is stored as 0), so
+            // its address is clamped to a valid one instead of tested.
             const vt pc = *reinterpret_cast<const vt*>(prow);
-            vt s;
+            vt s = *reinterpret_cast<const vt*>(Qs + j * LDQ + c);  // chain part, lam applied below
+            vt reg;
 #pragma unroll
-            for (int e = 0; e < E; ++e) s[e] = Tv(0);
+            for (int e = 0; e < E; ++e) reg[e] = Tv(0);
             if (has1) {
 #pragma unroll
-                for (int d = -2; d <= 2; ++d)
-                    if (j + d >= 0 && j + d < K)
-                        s += band1[j * 5 + d + 2] * *reinterpret_cast<const vt*>(prow + d * LDP);
+                for (int d = -2; d <= 2; ++d) {
+                    const int jj = min(max(j + d, 0), K - 1);
+                    reg += band1[j * 5 + d + 2] * *reinterpret_cast<const vt*>(Pw + jj * LDP + H + c);
+                }
             }
             if (hasN) {
                 Tv w[3 * E];
@@ -405,11 +411,9 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
                 const int i0 = t % nN;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    const int iN = i0 + e;
-                    const Tv* bN = bandN + iN * 5;
+                    const Tv* bN = bandN + (i0 + e) * 5;
 #pragma unroll
-                    for (int d = -2; d <= 2; ++d)
-                        if (iN + d >= 0 && iN + d < nN) s[e] += bN[d + 2] * w[E + e + d];
+                    for (int d = -2; d <= 2; ++d) reg[e] += bN[d + 2] * w[E + e + d];
                 }
             }
             for (int k = 1; k < N - 1; ++k) {
@@ -418,13 +422,16 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
                 const int sk = (int)st.stride[k], nk = (int)st.ext[k];
                 const int ik = (t / sk) % nk;
                 const Tv* br = rb + ik * 5;
-                s += br[2] * pc;
+                vt nbv[5];
 #pragma unroll
-                for (int d = -2; d <= 2; ++d)
-                    if (d != 0 && ik + d >= 0 && ik + d < nk)
-                        s += br[d + 2] * *reinterpret_cast<const vt*>(P + base + (int64_t)d * sk);
+                for (int d = -2; d <= 2; ++d) {
+                    const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
+                    nbv[d + 2] = *reinterpret_cast<const vt*>(P + base + (int64_t)dd * sk);
+                }
+#pragma unroll
+                for (int d = -2; d <= 2; ++d) reg += br[d + 2] * nbv[d + 2];
             }
-            const vt qv = *reinterpret_cast<const vt*>(Qs + j * LDQ + c) + lam * s;
+            const vt qv = s + lam * reg;
             *reinterpret_cast<vt*>(Q + base) = qv;
 #pragma unroll
             for (int e = 0; e < E; ++e) dot_acc += (double)pc[e] * (double)qv[e];
