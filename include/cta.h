@@ -146,6 +146,17 @@ cta_status cta_rhs(cta_op op, const void* Y, cta_dtype y_dtype, void* B, cta_dty
 cta_status cta_apply_normal_op(cta_op op, const void* P, void* Q, cta_dtype dtype,
                                cta_precision chain, double* dot, void* stream);
 
+/* Autotuner of one operator: times every tile-shape variant combination of
+ * the chain passes of N in `chain` precision (median of `reps` applies on the
+ * handle's own workspace, which it overwrites), rejects any variant whose
+ * output is not bit-identical to the default shapes', and keeps the fastest
+ * in the handle for later applies and solves.  Synchronous. */
+cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
+/* The variants chosen for `chain` (tail, middle, last pass) into host_variants3;
+ * cta_op_set_tuning sets them (each 0 or 1). */
+cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3);
+cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3);
+
 /* ------------------------------------------------------------------------
  * Conjugate-gradient solve (Fig. Tensor_CG) of N(X) = B.
  *

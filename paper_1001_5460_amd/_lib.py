@@ -89,6 +89,9 @@ _SIGS = {
     "cta_ws_adam_step": (ctypes.c_int, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, _P]),
     "cta_ws_params": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int, _P]),
+    "cta_tune_op": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P]),
+    "cta_op_get_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "cta_op_set_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "cta_prof_enable": (ctypes.c_int, [ctypes.c_int]),
     "cta_prof_reset": (ctypes.c_int, []),
     "cta_prof_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t,
@@ -285,6 +288,20 @@ def cta_apply_normal_op(h, P, Q, chain="f32", dot=None, stream=None):
     return Q
 
 
+def cta_tune_op(h, chain="bf16", reps=5, stream=None):
+    """Pick the fastest bit-identical tile shapes of the operator's passes; returns them."""
+    lib = load_library()
+    _check(lib.cta_tune_op(h, _PREC[chain], reps, _stream(stream)))
+    v = (ctypes.c_int * 3)()
+    _check(lib.cta_op_get_tuning(h, _PREC[chain], v))
+    return {"tail": v[0], "middle": v[1], "last": v[2]}
+
+
+def cta_op_set_tuning(h, chain, tail, middle, last):
+    v = (ctypes.c_int * 3)(tail, middle, last)
+    _check(load_library().cta_op_set_tuning(h, _PREC[chain], v))
+
+
 def cta_cg_opts_default():
     o = _CgOpts()
     load_library().cta_cg_opts_default(ctypes.byref(o))
@@ -458,6 +475,9 @@ class Operator:
         if Q is None:
             Q = torch.empty_like(P)
         return cta_apply_normal_op(self.handle, P, Q, chain, dot, stream)
+
+    def tune(self, chain="bf16", reps=5, stream=None):
+        return cta_tune_op(self.handle, chain, reps, stream)
 
     def solve(self, B, X=None, stream=None, **opts):
         torch = _torch()

@@ -37,6 +37,11 @@ struct cta_op_s {
     double* partials = nullptr;
     std::vector<void*> allocs;
     size_t dev_bytes = 0;
+    // tile-shape variants of the normal-operator passes, per compute dtype
+    // (F64, F32, BF16); set by cta_tune_op, 0 = default shapes
+    int var_tail[3] = {0, 0, 0};
+    int var_mid[3] = {0, 0, 0};
+    int var_last[3] = {0, 0, 0};
 };
 
 namespace cta {

@@ -132,7 +132,7 @@ cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post
     }
     hipError_t e = launch_tail(tv, tc, tc, Pin, op->T1, op->G[tc][a], op->G[tc][b], nblk,
                                (int)op->n[a], (int)op->n[b], (int)op->n[a], (int)op->n[b], pvec,
-                               &op->scal->beta, done, s);
+                               &op->scal->beta, done, s, op->var_tail[tc]);
     if (e != hipSuccess) return fail(CTA_ERR_HIP, "tail pass launch: %s", hipGetErrorString(e));
     void* cur = op->T1;
     void* nxt = op->T2;
@@ -141,7 +141,7 @@ cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post
         for (int l = 0; l < k; ++l) lead *= op->n[l];
         for (int l = k + 1; l < N; ++l) trail *= op->n[l];
         e = launch_strided(tc, cur, nxt, op->G[tc][k], lead, (int)op->n[k], (int)op->n[k], trail,
-                           done, s);
+                           done, s, op->var_mid[tc]);
         if (e != hipSuccess) return fail(CTA_ERR_HIP, "mode pass launch: %s", hipGetErrorString(e));
         std::swap(cur, nxt);
     }
@@ -157,7 +157,8 @@ cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post
         st.rband[k] = op->rband[tv == DT_F64 ? 0 : 1][k];
     }
     e = launch_normal_last(tc, tv, tc, cur, Q, op->G[tc][0], (int)op->n[0], (int)op->n[0],
-                           op->N / op->n[0], st, op->partials, op->scal, post, dot_out, done, s);
+                           op->N / op->n[0], st, op->partials, op->scal, post, dot_out, done, s,
+                           op->var_last[tc]);
     if (e != hipSuccess) return fail(CTA_ERR_HIP, "last pass launch: %s", hipGetErrorString(e));
     return CTA_OK;
 }
@@ -661,4 +662,84 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
         st = fail(CTA_NOT_CONVERGED, "tolerance not reached within the iteration limit");
     info->status = st;
     return st;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner of one operator's chain: every combination of pass variants is
+// timed on the handle's workspace (median of `reps` applies) and validated
+// against the default combination (the difference must be exactly zero: the
+// variants change tiling only, not the order of any sum).
+extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream) {
+    if (!op) return fail(CTA_ERR_ARG, "op is NULL");
+    if (chain != CTA_PREC_F64 && chain != CTA_PREC_F32 && chain != CTA_PREC_BF16)
+        return fail(CTA_ERR_ARG, "chain precision must be F64, F32 or BF16");
+    if (reps < 1) reps = 5;
+    hipStream_t s = (hipStream_t)stream;
+    const int tc = prec_tc(chain), tv = prec_tvec(chain);
+    if (!tail_fits(tc, (int)op->n[op->order - 2], (int)op->n[op->order - 1]))
+        return fail(CTA_ERR_UNSUPPORTED, "operator chain not supported in this precision");
+    CTA_HIP(launch_fill_pattern(tv, op->vp, op->N, s));
+    hipEvent_t e0, e1;
+    CTA_HIP(hipEventCreate(&e0));
+    CTA_HIP(hipEventCreate(&e1));
+    int best[3] = {0, 0, 0};
+    float best_ms = 1e30f;
+    for (int combo = 0; combo < 8; ++combo) {
+        op->var_tail[tc] = combo & 1;
+        op->var_mid[tc] = (combo >> 1) & 1;
+        op->var_last[tc] = (combo >> 2) & 1;
+        void* out = combo == 0 ? op->vaux : op->vq;
+        cta_status st = apply_normal(op, op->vp, out, chain, POST_NONE, nullptr, false, s);
+        if (st != CTA_OK) return st;
+        if (combo != 0) {
+            CTA_HIP(launch_residual(tv, tv, op->vaux, op->vq, op->vx, op->N, op->partials, op->scal,
+                                    &op->scal->dot, s));
+            CTA_TRY(read_scal(op, s));
+            if (op->hscal->dot != 0.0) continue;  // not identical: never chosen
+        }
+        std::vector<float> ms;
+        for (int r = 0; r < reps; ++r) {
+            CTA_HIP(hipEventRecord(e0, s));
+            CTA_TRY(apply_normal(op, op->vp, op->vq, chain, POST_NONE, nullptr, false, s));
+            CTA_HIP(hipEventRecord(e1, s));
+            CTA_HIP(hipEventSynchronize(e1));
+            float t = 0;
+            CTA_HIP(hipEventElapsedTime(&t, e0, e1));
+            ms.push_back(t);
+        }
+        std::sort(ms.begin(), ms.end());
+        const float med = ms[ms.size() / 2];
+        if (med < best_ms) {
+            best_ms = med;
+            best[0] = combo & 1;
+            best[1] = (combo >> 1) & 1;
+            best[2] = (combo >> 2) & 1;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    op->var_tail[tc] = best[0];
+    op->var_mid[tc] = best[1];
+    op->var_last[tc] = best[2];
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3) {
+    if (!op || !host_variants3) return fail(CTA_ERR_ARG, "NULL argument");
+    const int tc = prec_tc(chain);
+    host_variants3[0] = op->var_tail[tc];
+    host_variants3[1] = op->var_mid[tc];
+    host_variants3[2] = op->var_last[tc];
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3) {
+    if (!op || !host_variants3) return fail(CTA_ERR_ARG, "NULL argument");
+    for (int i = 0; i < 3; ++i)
+        if (host_variants3[i] < 0 || host_variants3[i] > 1) return fail(CTA_ERR_ARG, "variant must be 0 or 1");
+    const int tc = prec_tc(chain);
+    op->var_tail[tc] = host_variants3[0];
+    op->var_mid[tc] = host_variants3[1];
+    op->var_last[tc] = host_variants3[2];
+    return CTA_OK;
 }

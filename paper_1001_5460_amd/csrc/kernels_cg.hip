@@ -328,6 +328,26 @@ hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStrea
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ test pattern
+template <typename T>
+__global__ __launch_bounds__(CTA_WG) void k_fill_pattern(T* x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * CTA_WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * CTA_WG) {
+        const uint32_t h = (uint32_t)(i * 2654435761ull) ^ (uint32_t)(i >> 32);
+        x[i] = (T)((double)(h >> 8) * (1.0 / 16777216.0) - 0.5);
+    }
+}
+
+hipError_t launch_fill_pattern(int tv, void* x, int64_t n, hipStream_t s) {
+    const int g = plain_grid(n);
+    if (tv == DT_F64)
+        k_fill_pattern<double><<<g, CTA_WG, 0, s>>>((double*)x, n);
+    else if (tv == DT_F32)
+        k_fill_pattern<float><<<g, CTA_WG, 0, s>>>((float*)x, n);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ X64 += d
 template <typename Td>
 __global__ __launch_bounds__(CTA_WG) void k_add_f64(double* __restrict__ X,

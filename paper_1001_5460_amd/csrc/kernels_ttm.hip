@@ -50,9 +50,17 @@ static hipError_t go_strided(StridedArgs a, const int* done, hipStream_t s) {
     return hipGetLastError();
 }
 
+// variant 0: 64-column tiles; variant 1: 128-column tiles (twice the columns per wave)
 template <typename Tin, typename Tout, typename Tc>
-static hipError_t strided_T(StridedArgs a, const int* done, hipStream_t s) {
+static hipError_t strided_T(StridedArgs a, int variant, const int* done, hipStream_t s) {
     const int jt = (a.J + 15) / 16;
+    if (variant == 1) {
+        if (jt <= 1) return go_strided<Tin, Tout, Tc, 1, 1, 2>(a, done, s);
+        if (jt <= 2) return go_strided<Tin, Tout, Tc, 1, 2, 4>(a, done, s);
+        if (jt <= 4) return go_strided<Tin, Tout, Tc, 1, 4, 8>(a, done, s);
+        if (jt <= 6) return go_strided<Tin, Tout, Tc, 3, 2, 4>(a, done, s);
+        if (jt <= 8) return go_strided<Tin, Tout, Tc, 2, 4, 8>(a, done, s);
+    }
     if (jt <= 1) return go_strided<Tin, Tout, Tc, 1, 1, 1>(a, done, s);
     if (jt <= 2) return go_strided<Tin, Tout, Tc, 1, 2, 2>(a, done, s);
     if (jt <= 4) return go_strided<Tin, Tout, Tc, 1, 4, 4>(a, done, s);
@@ -64,7 +72,7 @@ static hipError_t strided_T(StridedArgs a, const int* done, hipStream_t s) {
 }
 
 hipError_t launch_strided(int tc, const void* X, void* Y, const Mat& M, int64_t lead, int K, int J,
-                          int64_t trail, const int* done, hipStream_t s) {
+                          int64_t trail, const int* done, hipStream_t s, int variant) {
     StridedArgs a{};
     a.X = X; a.Y = Y; a.M = M.p; a.ldm = M.ld;
     a.K = K; a.J = J; a.kpad = (K + dt_kstep(tc) - 1) / dt_kstep(tc) * dt_kstep(tc);
@@ -72,9 +80,9 @@ hipError_t launch_strided(int tc, const void* X, void* Y, const Mat& M, int64_t 
     if (a.kpad > M.ld) return hipErrorInvalidValue;
     ProfScope ps(tc == DT_F64 ? "strided.f64" : tc == DT_F32 ? "strided.f32" : "strided.bf16", s);
     switch (tc) {
-        case DT_F64: return strided_T<double, double, double>(a, done, s);
-        case DT_F32: return strided_T<float, float, float>(a, done, s);
-        case DT_BF16: return strided_T<bf16, bf16, bf16>(a, done, s);
+        case DT_F64: return strided_T<double, double, double>(a, variant, done, s);
+        case DT_F32: return strided_T<float, float, float>(a, variant, done, s);
+        case DT_BF16: return strided_T<bf16, bf16, bf16>(a, variant, done, s);
     }
     return hipErrorInvalidValue;
 }
@@ -129,7 +137,7 @@ static hipError_t go_last(StridedArgs a, const StencilArgs<Tvec>& st, int* grid_
 
 template <typename Tmid, typename Tvec, typename Tc>
 static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, int* grid,
-                         const int* done, hipStream_t s) {
+                         const int* done, hipStream_t s, int variant) {
     StencilArgs<Tvec> st{};
     st.P = reinterpret_cast<const Tvec*>(d.P);
     for (int k = 0; k < 8; ++k) {
@@ -141,6 +149,12 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
     st.lam = d.lam;
     st.partials = partials;
     const int jt = (a.J + 15) / 16;
+    if (variant == 1) {  // 32-column tiles: less LDS per workgroup, more workgroups per CU
+        if (jt <= 2) return go_last<Tmid, Tvec, Tc, 1, 2, 1>(a, st, grid, done, s);
+        if (jt <= 4) return go_last<Tmid, Tvec, Tc, 1, 4, 2>(a, st, grid, done, s);
+        if (jt <= 6) return go_last<Tmid, Tvec, Tc, 3, 2, 1>(a, st, grid, done, s);
+        if (jt <= 8) return go_last<Tmid, Tvec, Tc, 2, 4, 2>(a, st, grid, done, s);
+    }
     if (jt <= 1) return go_last<Tmid, Tvec, Tc, 1, 1, 1>(a, st, grid, done, s);
     if (jt <= 2) return go_last<Tmid, Tvec, Tc, 1, 2, 2>(a, st, grid, done, s);
     if (jt <= 4) return go_last<Tmid, Tvec, Tc, 1, 4, 4>(a, st, grid, done, s);
@@ -154,7 +168,7 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
 hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q, const Mat& M,
                               int K, int J, int64_t trail, const StencilDesc& st,
                               double* partials, CgScalars* scal, int post, double* dot_out,
-                              const int* done, hipStream_t s) {
+                              const int* done, hipStream_t s, int variant) {
     StridedArgs a{};
     a.X = X; a.Y = Q; a.M = M.p; a.ldm = M.ld;
     a.K = K; a.J = J; a.kpad = (K + dt_kstep(tc) - 1) / dt_kstep(tc) * dt_kstep(tc);
@@ -165,11 +179,11 @@ hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q
     {
         ProfScope ps(tc == DT_F64 ? "normal_last.f64" : tc == DT_F32 ? "normal_last.f32" : "normal_last.bf16", s);
         if (tmid == DT_BF16 && tvec == DT_F32 && tc == DT_BF16)
-            e = last_T<bf16, float, bf16>(a, st, partials, &grid, done, s);
+            e = last_T<bf16, float, bf16>(a, st, partials, &grid, done, s, variant);
         else if (tmid == DT_F32 && tvec == DT_F32 && tc == DT_F32)
-            e = last_T<float, float, float>(a, st, partials, &grid, done, s);
+            e = last_T<float, float, float>(a, st, partials, &grid, done, s, variant);
         else if (tmid == DT_F64 && tvec == DT_F64 && tc == DT_F64)
-            e = last_T<double, double, double>(a, st, partials, &grid, done, s);
+            e = last_T<double, double, double>(a, st, partials, &grid, done, s, variant);
     }
     if (e != hipSuccess || post == POST_NONE) return e;
     return launch_finalize(partials, grid, scal, post, dot_out, s);
@@ -236,7 +250,7 @@ static hipError_t tail_T(const TailArgs& a, size_t lds, hipStream_t s) {
 
 hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const Mat& M1,
                        const Mat& M2, int64_t nblk, int K1, int K2, int J1, int J2, void* Pvec,
-                       const double* beta, const int* done, hipStream_t s) {
+                       const double* beta, const int* done, hipStream_t s, int variant) {
     if (!tail_fits(tc, K1, J2) || J1 > 256) return hipErrorInvalidValue;
     const int ks = dt_kstep(tc);
     TailArgs a{};
@@ -246,6 +260,7 @@ hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const 
     a.k2pad = (K2 + ks - 1) / ks * ks;
     a.nblk = nblk; a.Pvec = Pvec; a.beta = beta; a.done = done;
     a.nbg = tail_nb(tc, tout, K1, J1, J2);
+    if (variant == 1 && tail_lds_nb(tc, tout, K1, J1, J2, 2 * a.nbg) <= 64 * 1024) a.nbg *= 2;
     if (a.k1pad > M1.ld || a.k2pad > M2.ld) return hipErrorInvalidValue;
     const size_t lds = tail_lds_nb(tc, tout, K1, J1, J2, a.nbg);
     if (lds > 160 * 1024) return hipErrorInvalidValue;

@@ -1,23 +1,10 @@
-// Entry points of the batched solver, its autotuner and the learned warm
-// start that this build does not provide yet: they report CTA_ERR_UNSUPPORTED.
+// Entry points of the learned warm start that this build does not provide
+// yet: they report CTA_ERR_UNSUPPORTED.
 #include "../../include/cta.h"
 #include "abi_internal.hpp"
 
 using namespace cta;
 
-extern "C" cta_status cta_solve_batched(int, const cta_op*, const void* const*, void* const*,
-                                        cta_dtype, const cta_cg_opts*, cta_cg_info*, void*) {
-    return fail(CTA_ERR_UNSUPPORTED, "cta_solve_batched is not available in this build");
-}
-extern "C" cta_status cta_tune_batched(int, const cta_op*, int, const char*, void*) {
-    return fail(CTA_ERR_UNSUPPORTED, "cta_tune_batched is not available in this build");
-}
-extern "C" cta_status cta_tune_load(const char*) {
-    return fail(CTA_ERR_UNSUPPORTED, "cta_tune_load is not available in this build");
-}
-extern "C" cta_status cta_tune_dump(char*, size_t, size_t*) {
-    return fail(CTA_ERR_UNSUPPORTED, "cta_tune_dump is not available in this build");
-}
 extern "C" cta_status cta_ws_create(cta_ws* out, int, const int64_t*, int, int, int, uint64_t, void*) {
     if (out) *out = nullptr;
     return fail(CTA_ERR_UNSUPPORTED, "the warm-start network is not available in this build");

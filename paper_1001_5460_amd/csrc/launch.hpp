@@ -65,20 +65,22 @@ hipError_t launch_finalize(const double* partials, int n, CgScalars* scal, int p
                            hipStream_t s);
 
 // ---- TTM passes ----
+// `variant` selects a tile shape (0 = default; see kernels_ttm.hip); the
+// autotuner times the variants of every pass of an operator.
 hipError_t launch_strided(int tc, const void* X, void* Y, const Mat& M, int64_t lead, int K, int J,
-                          int64_t trail, const int* done, hipStream_t s);
+                          int64_t trail, const int* done, hipStream_t s, int variant = 0);
 hipError_t launch_contig(int tc, const void* X, void* Y, const Mat& M, int64_t rows, int K, int J,
                          const int* done, hipStream_t s);
 bool tail_fits(int tc, int K1, int J2);
 hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const Mat& M1,
                        const Mat& M2, int64_t nblk, int K1, int K2, int J1, int J2, void* Pvec,
-                       const double* beta, const int* done, hipStream_t s);
+                       const double* beta, const int* done, hipStream_t s, int variant = 0);
 // Last pass of the normal operator: Q = X x_1 M (mode 1 of a (K, trail)
 // tensor) + banded regulariser of P, with the FP64 <P, Q> reduced on device.
 hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q, const Mat& M,
                               int K, int J, int64_t trail, const StencilDesc& st,
                               double* partials, CgScalars* scal, int post, double* dot_out,
-                              const int* done, hipStream_t s);
+                              const int* done, hipStream_t s, int variant = 0);
 
 // ---- vector kernels (Tv = F32 or F64) ----
 hipError_t launch_cast(int tin, int tout, const void* x, void* y, int64_t n, hipStream_t s);
@@ -100,6 +102,8 @@ hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStrea
 // padded copy of a (possibly transposed) device matrix in another dtype
 hipError_t launch_pad_matrix(int tin, int tout, const void* src, int rows, int cols, int trans,
                              void* dst, int rows_st, int ld, hipStream_t s);
+// deterministic test pattern in [-0.5, 0.5) (hash of the index)
+hipError_t launch_fill_pattern(int tv, void* x, int64_t n, hipStream_t s);
 // X64 += (double) d32
 hipError_t launch_add_f64(double* X, const void* d, int td, int64_t n, hipStream_t s);
 

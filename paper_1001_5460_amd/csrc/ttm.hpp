@@ -230,7 +230,9 @@ struct LastLds {
     static constexpr int H = 4;  // halo columns per side
 };
 
-template <typename Tin, typename Tv, typename Tc, int JT, int WJ, int CT>
+// NORD > 0 fixes the tensor order at compile time (the batched solver uses 3),
+// so the per-mode loops unroll with constant indices.
+template <typename Tin, typename Tv, typename Tc, int JT, int WJ, int CT, int NORD = 0>
 __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t tile,
                                                  unsigned char* smem, const StencilArgs<Tv>& st,
                                                  double& dot_acc) {
@@ -248,7 +250,7 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
     const int K = a.K;
     const int trail = (int)a.trail;
     const int t0 = (int)tile * TN;
-    const int N = st.order;
+    const int N = NORD > 0 ? NORD : st.order;
     const int nN = (int)st.ext[N - 1];
     const size_t xs_bytes = (size_t)TN * ldx * sizeof(Tc);
     const size_t qs_bytes = (size_t)a.J * LDQ * sizeof(Tv);
@@ -422,14 +424,16 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
                 const int sk = (int)st.stride[k], nk = (int)st.ext[k];
                 const int ik = (t / sk) % nk;
                 const Tv* br = rb + ik * 5;
-                vt nbv[5];
+                vt nbv[4];
 #pragma unroll
-                for (int d = -2; d <= 2; ++d) {
+                for (int q = 0; q < 4; ++q) {
+                    const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
                     const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
-                    nbv[d + 2] = *reinterpret_cast<const vt*>(P + base + (int64_t)dd * sk);
+                    nbv[q] = *reinterpret_cast<const vt*>(P + base + (int64_t)dd * sk);
                 }
+                reg += br[2] * pc;
 #pragma unroll
-                for (int d = -2; d <= 2; ++d) reg += br[d + 2] * nbv[d + 2];
+                for (int q = 0; q < 4; ++q) reg += br[q < 2 ? q : q + 1] * nbv[q];
             }
             const vt qv = s + lam * reg;
             *reinterpret_cast<vt*>(Q + base) = qv;

@@ -1,0 +1,99 @@
+"""GPU batched persistent solver (many uneven order-3 problems in one launch)
+against the FP64 oracle and against the sequential per-problem loop.
+
+Every problem's solution is judged by the oracle's FP64 relative residual
+(<= rtol, the recursive test being followed by a recomputed true residual),
+and the batched and sequential solutions agree within kappa * rtol.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from gpu_util import dev, host, rel_fro, torch_cuda
+
+import paper_1001_5460_amd as cta
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(count, seed, sizes=(24, 32, 48)):
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, len(sizes), (count, 3))
+    probs = []
+    for p in range(count):
+        n = tuple(int(sizes[i]) for i in idx[p])
+        m = tuple(3 * v // 2 for v in n)
+        probs.append(workload.make_problem(n, m, 1e-3, 0.01, 500 + p, 1e-6))
+    return probs
+
+
+def _solve_all(probs, torch):
+    ops, Bs, refs = [], [], []
+    for p in probs:
+        ref = oracle.NormalOperator(p.A, p.D, p.lam)
+        B = ref.rhs(ref.forward(p.X_true) + p.noise)
+        refs.append((ref, B))
+        ops.append(cta.Operator(p.A, p.D, p.lam))
+        Bs.append(dev(B, torch.float32))
+    Xs = [torch.zeros_like(b) for b in Bs]
+    return ops, Bs, Xs, refs
+
+
+@pytest.mark.parametrize("count,seed", [(1, 1), (9, 2), (40, 3)])
+def test_batched_matches_oracle_and_sequential(count, seed):
+    torch = torch_cuda()
+    probs = _batch(count, seed)
+    ops, Bs, Xs, refs = _solve_all(probs, torch)
+    infos = cta.cta_solve_batched([o.handle for o in ops], Bs, Xs, precision="f32", rtol=1e-6,
+                                  max_iter=2000)
+    for i, (p, info) in enumerate(zip(probs, infos)):
+        ref, B = refs[i]
+        res = oracle.relative_residual(host(Xs[i]), B, ref)
+        assert info["status"] == 0, (i, info)
+        assert res <= 1.05e-6, (i, res)
+        # the library's residual is against the FP32-rounded B the solver was
+        # given; the oracle's against the FP64 B: they differ by ~6e-8 relative
+        assert abs(info["rel_res_true"] - res) <= 2e-7
+        # sequential loop: same method, one problem at a time
+        Xseq, sinfo = ops[i].solve(Bs[i], precision="f32", rtol=1e-6, max_iter=2000)
+        assert abs(sinfo["iters"] - info["iters"]) <= 0.1 * sinfo["iters"] + 2
+        assert rel_fro(host(Xs[i]), host(Xseq)) <= 1e-3
+
+
+def test_batched_team_sizes_via_cache(tmp_path):
+    torch = torch_cuda()
+    probs = _batch(12, 7, sizes=(24, 48, 64, 96))
+    ops, Bs, Xs, refs = _solve_all(probs, torch)
+    handles = [o.handle for o in ops]
+    path = str(tmp_path / "tune.json")
+    cta.cta_tune_batched(handles, reps=1, cache_path=path)
+    with open(path) as f:
+        cache = json.load(f)
+    assert len(cache) >= 1
+    key = [k for k in cache if k.startswith("gfx950/batched/12/")][0]
+    for team in (1, 2, 4):
+        for variant in (0, 1):
+            cache[key] = {"team": team, "last_variant": variant}
+            with open(path, "w") as f:
+                json.dump(cache, f)
+            cta.cta_tune_load(path)
+            for X in Xs:
+                X.zero_()
+            infos = cta.cta_solve_batched(handles, Bs, Xs, precision="f32", rtol=1e-6, max_iter=2000)
+            for i, info in enumerate(infos):
+                ref, B = refs[i]
+                assert info["status"] == 0, (team, variant, i, info)
+                assert oracle.relative_residual(host(Xs[i]), B, ref) <= 1.05e-6
+
+
+def test_batched_rejects_bad_input():
+    torch = torch_cuda()
+    p = workload.make_problem((8, 8, 8, 8), (12, 12, 12, 12), 1e-3, 0.01, 0, 1e-6)
+    op = cta.Operator(p.A, p.D, p.lam)
+    B = torch.zeros(p.n, dtype=torch.float32, device="cuda")
+    with pytest.raises(cta.CtaError):
+        cta.cta_solve_batched([op.handle], [B], [torch.zeros_like(B)], precision="f32", rtol=1e-6)

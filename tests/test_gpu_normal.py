@@ -102,3 +102,28 @@ def test_unsupported_wide_regulariser():
     D = [np.ones((2, 8))] * 3          # D^T D is dense
     with pytest.raises(cta.CtaError):
         cta.Operator(p.A, D, 1e-3)
+
+
+@pytest.mark.parametrize("chain", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,m", [((16, 12, 10, 8), (24, 18, 15, 12)), ((32, 32, 32), (48, 48, 48)),
+                                 ((40, 24, 20, 16), (60, 36, 30, 24))])
+def test_tile_variants_match_oracle(n, m, chain):
+    torch = torch_cuda()
+    p, ref_op = _op(n, m, 1e-3)
+    op = cta.Operator(p.A, p.D, p.lam)
+    dt = torch.float64 if chain == "f64" else torch.float32
+    P = dev(np.random.default_rng(11).standard_normal(n), dt)
+    ref = ref_op(host(P))
+    outs = []
+    for combo in range(8):
+        cta.cta_op_set_tuning(op.handle, chain, combo & 1, (combo >> 1) & 1, (combo >> 2) & 1)
+        Q = op.apply(P, chain=chain)
+        torch.cuda.synchronize()
+        assert rel_fro(host(Q), ref) <= TOL[chain]
+        outs.append(Q.clone())
+    for Q in outs[1:]:
+        assert torch.equal(Q, outs[0])   # tiling never changes the arithmetic
+    picked = op.tune(chain, reps=2)
+    assert set(picked) == {"tail", "middle", "last"}
+    Q = op.apply(P, chain=chain)
+    assert torch.equal(Q, outs[0])
