@@ -56,8 +56,18 @@ def _basis_row(t, knots, n, degree):
     return b
 
 
+_CACHE = {}
+
+
 def collocation_matrix(m, n, degree=3):
     """m x n matrix: entry (i, j) is basis function j at sample t_i = i/(m-1)."""
+    key = (int(m), int(n), int(degree))
+    if key not in _CACHE:
+        _CACHE[key] = _collocation(*key)
+    return _CACHE[key].copy()
+
+
+def _collocation(m, n, degree):
     if m < 2:
         raise ValueError("need at least two sample points")
     knots = clamped_knots(n, degree)
