@@ -36,11 +36,12 @@ from .normal import (
 from .cg import cg, CGResult, lanczos_extremes
 from .dense import assemble, dense_solve
 from .judge import relative_residual
+from . import wsnet
 
 __all__ = [
     "mode_product", "multi_mode_product", "inner",
     "gram", "reg_factor", "forward", "rhs", "normal_apply",
     "normal_apply_literal", "regulariser_apply", "NormalOperator",
     "cg", "CGResult", "lanczos_extremes",
-    "assemble", "dense_solve", "relative_residual",
+    "assemble", "dense_solve", "relative_residual", "wsnet",
 ]

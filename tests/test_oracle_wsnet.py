@@ -1,0 +1,96 @@
+"""Pins of the warm-start network oracle (separable convolutions, Table 1;
+gradients by the derivative rule of App. A.8)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import wsnet
+
+
+def _rand_params(C, width, blocks, order, seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return wsnet.unpack(scale * rng.standard_normal(wsnet.param_count(C, width, blocks, order)),
+                        C, width, blocks, order)
+
+
+def test_headline_parameter_count():
+    assert wsnet.param_count(32, 5, 5, 4) == 103137
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_conv_is_toeplitz_mode_product(k):
+    # Table 1: a 1-D convolution along a mode is a mode product with a banded
+    # Toeplitz matrix; with channels it is a sum of such products per channel pair
+    rng = np.random.default_rng(1 + k)
+    shape = (7, 6, 5)
+    Cin, Cout, width = 3, 2, 5
+    z = rng.standard_normal((Cin,) + shape)
+    W = rng.standard_normal((Cout, Cin, width))
+    out = wsnet.conv(z, W, k)
+    n = shape[k]
+    for co in range(Cout):
+        ref = np.zeros(shape)
+        for ci in range(Cin):
+            T = np.zeros((n, n))
+            for i in range(n):
+                for ip in range(n):
+                    if abs(ip - i) <= width // 2:
+                        T[i, ip] = W[co, ci, ip - i + width // 2]
+            ref += oracle.mode_product(z[ci], T, k)
+        np.testing.assert_allclose(out[co], ref, rtol=1e-13, atol=1e-13)
+
+
+def test_gradient_matches_central_differences():
+    C, width, blocks, order = 4, 5, 2, 4
+    shape = (6, 5, 4, 3)
+    rng = np.random.default_rng(3)
+    theta = 0.3 * rng.standard_normal(wsnet.param_count(C, width, blocks, order))
+    B = rng.standard_normal(shape)
+    T = rng.standard_normal(shape)
+    L0, g = wsnet.mse_loss(wsnet.unpack(theta, C, width, blocks, order), B, T)
+    h = 1e-6
+    fd = np.zeros_like(theta)
+    for i in range(theta.size):
+        tp = theta.copy()
+        tp[i] += h
+        tm = theta.copy()
+        tm[i] -= h
+        Lp, _ = wsnet.mse_loss(wsnet.unpack(tp, C, width, blocks, order), B, T)
+        Lm, _ = wsnet.mse_loss(wsnet.unpack(tm, C, width, blocks, order), B, T)
+        fd[i] = (Lp - Lm) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-9)
+
+
+def test_linear_without_activation():
+    P = _rand_params(3, 5, 2, 3, seed=5)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((5, 4, 6))
+    y = rng.standard_normal((5, 4, 6))
+    f0 = wsnet.forward(P, np.zeros_like(x), relu=False)
+    fx = wsnet.forward(P, x, relu=False) - f0
+    fy = wsnet.forward(P, y, relu=False) - f0
+    fxy = wsnet.forward(P, 2.0 * x - 0.5 * y, relu=False) - f0
+    np.testing.assert_allclose(fxy, 2.0 * fx - 0.5 * fy, rtol=1e-11, atol=1e-11)
+
+
+def test_warm_start_scale_equivariant():
+    P = _rand_params(3, 5, 1, 3, seed=7)
+    B = np.random.default_rng(8).standard_normal((5, 4, 6))
+    np.testing.assert_allclose(wsnet.warm_start(P, 4.0 * B), 4.0 * wsnet.warm_start(P, B),
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_adam_first_step_is_sign_step():
+    rng = np.random.default_rng(9)
+    theta = rng.standard_normal(20)
+    g = rng.standard_normal(20)
+    new, m, v = wsnet.adam_step(theta, g, np.zeros(20), np.zeros(20), 1, lr=1e-2, eps=0.0)
+    np.testing.assert_allclose(new, theta - 1e-2 * np.sign(g), rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_pack_unpack_roundtrip():
+    C, width, blocks, order = 4, 5, 2, 4
+    theta = np.arange(wsnet.param_count(C, width, blocks, order), dtype=float)
+    assert np.array_equal(wsnet.pack(wsnet.unpack(theta, C, width, blocks, order)), theta)
