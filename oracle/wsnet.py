@@ -17,8 +17,9 @@ Architecture for an order-N input tensor b (extents n):
             h  = h + conv_N(z_{N-1}) + cN                      (mode N, residual)
     out     = sum_c pw[c] * h[c] + pb                         (projection, C -> 1)
 conv_k(z)[co, i] = sum_{ci, w} W[co, ci, w] * z[ci, i + (w - width//2) e_k] with
-zero padding.  The warm start for a right-hand side B is X0 = s * out(B / s),
-s = ||B||_2.
+zero padding.  The warm start for a right-hand side B is X0 = s * out(B / s)
+with s the RMS of B (||B||_2 / sqrt(#entries)): N^{-1} is linear, so the
+network sees inputs of unit RMS whatever the scale of B.
 
 Flat parameter layout (shared with the GPU library):
     lw (C), lb (C), then for each block and each mode k: W_k (C*C*width, index
@@ -166,17 +167,22 @@ def backward(P, acts, dout, relu=True):
     return G
 
 
+def rms(B):
+    B = np.asarray(B, dtype=np.float64)
+    return float(np.linalg.norm(B) / np.sqrt(B.size))
+
+
 def warm_start(P, B, relu=True):
-    """X0 = s * f(B / s), s = ||B||_2."""
-    s = float(np.linalg.norm(np.asarray(B, dtype=np.float64)))
+    """X0 = s * f(B / s), s = RMS of B."""
+    s = rms(B)
     if s == 0.0:
         return np.zeros_like(B, dtype=np.float64)
     return s * forward(P, np.asarray(B) / s, relu=relu)
 
 
 def mse_loss(P, B, T, relu=True):
-    """L = mean((f(B/s) - T/s)^2) and dL/dtheta (flat), s = ||B||."""
-    s = float(np.linalg.norm(np.asarray(B, dtype=np.float64)))
+    """L = mean((f(B/s) - T/s)^2) and dL/dtheta (flat), s = RMS of B."""
+    s = rms(B)
     out, acts = forward(P, np.asarray(B) / s, relu=relu, keep=True)
     diff = out - np.asarray(T, dtype=np.float64) / s
     L = float(np.mean(diff ** 2))
