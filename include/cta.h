@@ -233,13 +233,20 @@ cta_status cta_tune_dump(char* host_buf, size_t bytes, size_t* needed);
  * Learned warm start: a separable network (per-mode 1-D convolutions, the
  * convolution row of Table 1) mapping B to a starting tensor X0.
  *
- * Architecture (order 4 tensors only): input B / ||B||; pointwise lift
- * 1 -> C channels; `blocks` residual blocks, each four convolutions of width
- * `width` along modes 1..4 (zero padding, C -> C channels, bias) with ReLU
- * after the first three; pointwise projection C -> 1; output times ||B||.
- * FP32 master weights and Adam state; BF16 copies of weights and
- * activations in the convolutions with FP32 accumulation on MFMA.
- * C must be 32 and width 5 in this build.
+ * Architecture (order 4 tensors only), with s = RMS of B (||B|| / sqrt(size)):
+ *   h0 = lw * (B / s) + lb                  pointwise lift 1 -> C channels
+ *   `blocks` residual blocks: four convolutions of width `width` along modes
+ *   1..4 (zero padding, C -> C channels, bias), ReLU after the first three,
+ *   the fourth added to the block input
+ *   X0 = s * (pw . h + pb)                  pointwise projection C -> 1
+ * s depends on B only, so no gradient flows through it.  FP32 master
+ * parameters and Adam state; BF16 copies of the convolution weights and of
+ * the activations, FP32 accumulation on MFMA.  C must be 32 and width 5.
+ *
+ * Flat FP32 parameter layout (cta_ws_params): lw[C], lb[C]; for each block
+ * and each mode k: W_k[(co*C + ci)*width + w] (C*C*width entries), then the
+ * bias c_k[C]; then pw[C], pb.  Memory: (blocks*4 + 4) activation tensors of
+ * 64 bytes per entry are allocated at creation.
  * ---------------------------------------------------------------------- */
 typedef struct cta_ws_s* cta_ws;
 
@@ -248,15 +255,16 @@ cta_status cta_ws_create(cta_ws* out, int order, const int64_t* n, int channels,
 cta_status cta_ws_destroy(cta_ws w);
 /* Number of FP32 parameters. */
 int64_t cta_ws_num_params(cta_ws w);
-/* X0 = f(B) for one F32 tensor B (extents n).  training != 0 keeps the
- * activations for cta_ws_backward.  Asynchronous. */
+/* X0 = s * f(B / s) for one F32 tensor B (extents n, row-major), X0 F32.
+ * The activations are always kept for cta_ws_backward (`training` is
+ * accepted for interface stability).  Asynchronous. */
 cta_status cta_ws_forward(cta_ws w, const void* B, void* X0, int training, void* stream);
 /* Given dL/dX0 (F32, extents n) of the last training forward, accumulate the
  * parameter gradient.  Asynchronous. */
 cta_status cta_ws_backward(cta_ws w, const void* dX0, void* stream);
-/* Mean-squared-error loss L = mean((X0 - T)^2) of the last forward output X0
- * against target T (F32): writes dL/dX0 to dX0 and L to the device double
- * *loss (may be NULL).  Asynchronous. */
+/* Scale-free mean-squared error of the last forward output X0 against the
+ * target T (F32): L = mean(((X0 - T) / s)^2).  Writes dL/dX0 to dX0 and L to
+ * the DEVICE double *loss (may be NULL).  Asynchronous. */
 cta_status cta_ws_mse(cta_ws w, const void* X0, const void* T, void* dX0, double* loss,
                       void* stream);
 /* Zero the accumulated gradient.  Asynchronous. */

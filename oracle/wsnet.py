@@ -21,11 +21,32 @@ zero padding.  The warm start for a right-hand side B is X0 = s * out(B / s)
 with s the RMS of B (||B||_2 / sqrt(#entries)): N^{-1} is linear, so the
 network sees inputs of unit RMS whatever the scale of B.
 
+Storage precision model.  The warm-start form fixes BF16 weights and
+activations with FP32 accumulation.  Every function below takes an optional
+``store`` callable (``bf16_round`` or None): when given, the convolution
+weights and every stored activation and activation gradient (h, z, the
+gradients between convolutions) are rounded with it, while sums stay in
+float64.  With store=None the network is exact float64.
+
 Flat parameter layout (shared with the GPU library):
     lw (C), lb (C), then for each block and each mode k: W_k (C*C*width, index
     (co*C + ci)*width + w) and c_k (C); then pw (C), pb (1).
 """
 import numpy as np
+
+
+def bf16_round(x):
+    """Round to the nearest BF16 value (ties to even) via float32: keep the
+    upper 16 bits of the float32 pattern after adding half an ulp of BF16
+    (0x7fff plus the lowest kept bit)."""
+    x32 = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    bits = x32.view(np.uint32).astype(np.uint64)
+    bits = (bits + 0x7FFF + ((bits >> 16) & 1)) & 0xFFFF0000
+    return bits.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(x))
+
+
+def _ident(x):
+    return x
 
 
 def param_count(C, width, blocks, order):
@@ -107,40 +128,43 @@ def conv_backward(g, zin, W, k):
     return dz, dW
 
 
-def forward(P, b, relu=True, keep=False):
+def forward(P, b, relu=True, keep=False, store=None):
     """Network output for a normalised input b (no scaling).  keep=True also
     returns the activations needed by backward()."""
+    st = store or _ident
     b = np.asarray(b, dtype=np.float64)
     order = b.ndim
     h = P["lw"][:, None] * b.reshape(1, -1) + P["lb"][:, None]
-    h = h.reshape((-1,) + b.shape)
+    h = st(h.reshape((-1,) + b.shape))
     acts = {"b": b, "h": [h], "z": []}
     act = (lambda x: np.maximum(x, 0.0)) if relu else (lambda x: x)
     for Ws, cs in zip(P["W"], P["c"]):
         zs = []
         z = h
         for k in range(order):
-            y = conv(z, Ws[k], k) + cs[k].reshape((-1,) + (1,) * order)
+            y = conv(z, st(Ws[k]), k) + cs[k].reshape((-1,) + (1,) * order)
             if k < order - 1:
-                z = act(y)
+                z = st(act(y))
                 zs.append(z)
             else:
-                h = h + y
+                h = st(h + y)
         acts["z"].append(zs)
         acts["h"].append(h)
     out = np.tensordot(P["pw"], h, axes=([0], [0])) + P["pb"]
     return (out, acts) if keep else out
 
 
-def backward(P, acts, dout, relu=True):
-    """Gradient (same dict structure as P) of sum(dout * forward(P, b))."""
+def backward(P, acts, dout, relu=True, store=None):
+    """Gradient (same dict structure as P) of sum(dout * forward(P, b)); pass
+    the same ``store`` as to the forward that produced ``acts``."""
+    st = store or _ident
     b = acts["b"]
     order = b.ndim
     G = {"lw": None, "lb": None, "W": [], "c": [], "pw": None, "pb": None}
     h_last = acts["h"][-1]
     G["pw"] = np.tensordot(h_last, dout, axes=(list(range(1, h_last.ndim)), list(range(dout.ndim))))
     G["pb"] = float(np.sum(dout))
-    dh = P["pw"].reshape((-1,) + (1,) * order) * dout[None]
+    dh = st(P["pw"].reshape((-1,) + (1,) * order) * dout[None])
     nblocks = len(P["W"])
     Wg = [None] * nblocks
     cg = [None] * nblocks
@@ -153,12 +177,12 @@ def backward(P, acts, dout, relu=True):
         for k in reversed(range(order)):
             zin = hin if k == 0 else zs[k - 1]
             cg[bi][k] = np.sum(g, axis=tuple(range(1, g.ndim)))
-            dz, dW = conv_backward(g, zin, Ws[k], k)
+            dz, dW = conv_backward(g, zin, st(Ws[k]), k)
             Wg[bi][k] = dW
             if k > 0:
-                g = dz * (zs[k - 1] > 0) if relu else dz
+                g = st(dz * (zs[k - 1] > 0) if relu else dz)
             else:
-                dh = dh + dz  # residual skip plus the path through the block
+                dh = st(dh + dz)  # residual skip plus the path through the block
     G["W"] = Wg
     G["c"] = cg
     h0grad = dh
@@ -172,22 +196,22 @@ def rms(B):
     return float(np.linalg.norm(B) / np.sqrt(B.size))
 
 
-def warm_start(P, B, relu=True):
+def warm_start(P, B, relu=True, store=None):
     """X0 = s * f(B / s), s = RMS of B."""
     s = rms(B)
     if s == 0.0:
         return np.zeros_like(B, dtype=np.float64)
-    return s * forward(P, np.asarray(B) / s, relu=relu)
+    return s * forward(P, np.asarray(B) / s, relu=relu, store=store)
 
 
-def mse_loss(P, B, T, relu=True):
+def mse_loss(P, B, T, relu=True, store=None):
     """L = mean((f(B/s) - T/s)^2) and dL/dtheta (flat), s = RMS of B."""
     s = rms(B)
-    out, acts = forward(P, np.asarray(B) / s, relu=relu, keep=True)
+    out, acts = forward(P, np.asarray(B) / s, relu=relu, keep=True, store=store)
     diff = out - np.asarray(T, dtype=np.float64) / s
     L = float(np.mean(diff ** 2))
     dout = 2.0 * diff / diff.size
-    G = backward(P, acts, dout, relu=relu)
+    G = backward(P, acts, dout, relu=relu, store=store)
     return L, pack(G)
 
 

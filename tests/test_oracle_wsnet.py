@@ -94,3 +94,56 @@ def test_pack_unpack_roundtrip():
     C, width, blocks, order = 4, 5, 2, 4
     theta = np.arange(wsnet.param_count(C, width, blocks, order), dtype=float)
     assert np.array_equal(wsnet.pack(wsnet.unpack(theta, C, width, blocks, order)), theta)
+
+
+def test_bf16_round_ties_to_even():
+    u = 2.0 ** -8  # half an ulp of BF16 at 1.0
+    x = np.array([1.0 + u, 1.0 + 3 * u, 1.0 + u + 2.0 ** -20, -(1.0 + u), 3.0, 0.0, 2.0 ** -130])
+    want = np.array([1.0, 1.0 + 4 * u, 1.0 + 2 * u, -1.0, 3.0, 0.0, 2.0 ** -130])
+    assert np.array_equal(wsnet.bf16_round(x), want)
+
+
+def test_bf16_round_matches_torch():
+    torch = pytest.importorskip("torch")
+    x = np.random.default_rng(5).standard_normal(10000) * 10.0 ** np.random.default_rng(6).integers(-6, 6, 10000)
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(wsnet.bf16_round(x), ref)
+
+
+def test_store_model_exact_on_representable_values():
+    """With integer weights in {-1, 0, 1}, zero biases and small integer
+    inputs every activation is a small integer, exact in BF16: the storage
+    model must then reproduce the exact network bit for bit."""
+    rng = np.random.default_rng(8)
+    C, width, blocks, order = 4, 5, 1, 3
+    theta = rng.integers(-1, 2, wsnet.param_count(C, width, blocks, order)).astype(np.float64)
+    P = wsnet.unpack(theta, C, width, blocks, order)
+    for cs in P["c"]:
+        for c in cs:
+            c[:] = 0.0
+    P["lb"][:] = 0.0
+    b = rng.integers(-1, 2, (3, 4, 3)).astype(np.float64)
+    exact = wsnet.forward(P, b)
+    assert np.max(np.abs(exact)) < 256
+    assert np.array_equal(wsnet.forward(P, b, store=wsnet.bf16_round), exact)
+    _, acts = wsnet.forward(P, b, keep=True)
+    _, acts_s = wsnet.forward(P, b, keep=True, store=wsnet.bf16_round)
+    dout = rng.integers(-1, 2, b.shape).astype(np.float64)
+    G = wsnet.pack(wsnet.backward(P, acts, dout))
+    Gs = wsnet.pack(wsnet.backward(P, acts_s, dout, store=wsnet.bf16_round))
+    assert np.array_equal(G, Gs)
+
+
+def test_store_model_rounds_activations():
+    """With BF16 storage every kept activation is a BF16 value and the output
+    moves away from the exact one by about the BF16 unit roundoff."""
+    C, width, blocks, order = 8, 5, 2, 3
+    theta = np.random.default_rng(9).standard_normal(wsnet.param_count(C, width, blocks, order)) * 0.2
+    P = wsnet.unpack(theta, C, width, blocks, order)
+    b = np.random.default_rng(10).standard_normal((5, 6, 4))
+    out, acts = wsnet.forward(P, b, keep=True, store=wsnet.bf16_round)
+    for t in acts["h"] + [z for zs in acts["z"] for z in zs]:
+        assert np.array_equal(wsnet.bf16_round(t), t)
+    exact = wsnet.forward(P, b)
+    rel = np.linalg.norm(out - exact) / np.linalg.norm(exact)
+    assert 1e-5 < rel < 3e-2

@@ -49,3 +49,17 @@ def test_blob_field():
     p = workload.warmstart_problem(3, n=(16, 12, 10, 8), m=(24, 18, 15, 12))
     assert p.X_true.shape == (16, 12, 10, 8)
     assert np.isfinite(p.X_true).all()
+
+
+def test_blob_field_torch_deterministic_and_shaped():
+    torch = pytest.importorskip("torch")
+    X1, _ = workload.blob_field_torch((6, 7, 5, 4), 12, device="cpu")
+    X2, _ = workload.blob_field_torch((6, 7, 5, 4), 12, device="cpu")
+    X3, _ = workload.blob_field_torch((6, 7, 5, 4), 13, device="cpu")
+    assert X1.dtype == torch.float32 and tuple(X1.shape) == (6, 7, 5, 4)
+    assert torch.equal(X1, X2) and not torch.equal(X1, X3)
+    # without the white noise the field is a sum of at most 8 separable blobs
+    Xn, _ = workload.blob_field_torch((6, 7, 5, 4), 12, noise_sigma=0.0, device="cpu")
+    M = Xn.double().reshape(6, -1).numpy()
+    assert np.linalg.matrix_rank(M, tol=1e-6 * np.abs(M).max()) <= 8
+    assert float(Xn.abs().max()) <= 8 * 2.0 + 1e-6

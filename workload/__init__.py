@@ -18,6 +18,8 @@ from .problems import (
     batched_sizes,
     batched_problem,
     blob_field,
+    blob_field_torch,
+    factors,
     warmstart_problem,
     integer_tensor,
     CONFIGS,
@@ -32,6 +34,8 @@ __all__ = [
     "batched_sizes",
     "batched_problem",
     "blob_field",
+    "blob_field_torch",
+    "factors",
     "warmstart_problem",
     "integer_tensor",
     "CONFIGS",

@@ -138,6 +138,41 @@ def blob_field(n, rng, noise_sigma=0.1):
     return X
 
 
+def blob_field_torch(n, seed, noise_sigma=0.1, device="cuda"):
+    """The recipe of blob_field, drawn with torch so that thousands of fields
+    can be made on the device (training data of the warm start).
+
+    The small draws (blob count, amplitudes, signs, centres, widths) come from
+    a CPU torch generator seeded with ``seed``; the white noise from a device
+    generator seeded with ``seed`` (returned, so that further draws for the
+    same sample continue its stream).  Float32.
+    """
+    import torch
+
+    n = tuple(int(v) for v in n)
+    g = torch.Generator(device="cpu").manual_seed(int(seed))
+    K = int(torch.randint(1, 9, (1,), generator=g))
+    X = torch.zeros(n, dtype=torch.float32, device=device)
+    for _ in range(K):
+        u = torch.rand(2, generator=g, dtype=torch.float64)
+        amp = (0.5 + 1.5 * float(u[0])) * (1.0 if float(u[1]) < 0.5 else -1.0)
+        blob = None
+        for k, nk in enumerate(n):
+            cw = torch.rand(2, generator=g, dtype=torch.float64)
+            c = float(cw[0]) * (nk - 1.0)
+            w = 1.5 + float(cw[1]) * (nk / 4.0 - 1.5)
+            i = torch.arange(nk, dtype=torch.float32, device=device)
+            prof = torch.exp(-0.5 * ((i - c) / w) ** 2)
+            shape = [1] * len(n)
+            shape[k] = nk
+            prof = prof.reshape(shape)
+            blob = prof if blob is None else blob * prof
+        X += amp * blob
+    gd = torch.Generator(device=device).manual_seed(int(seed))
+    X += noise_sigma * torch.randn(n, generator=gd, device=device, dtype=torch.float32)
+    return X, gd
+
+
 def warmstart_problem(seed, n=None, m=None, with_data=True):
     """Warm-start workload instance: blob X_true, noise sigma=0.01 on Y."""
     cfg = CONFIGS[4]
