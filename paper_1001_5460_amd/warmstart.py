@@ -128,20 +128,35 @@ def lr_at(step, total, lr0, lr_min=1e-5, warmup=50):
     return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * min(1.0, t)))
 
 
-def train(n, m, lam, samples, batch=4, blocks=5, lr=1e-3, seed0=0, target_rtol=1e-5,
-          log_every=100, log=print, net_seed=0):
-    """Train a fresh network on `samples` generated solves (seeds seed0..);
-    every sample is used once.  Returns the network and a training record."""
+def validation_loss(net, smp, pairs):
+    """Mean loss of the network over fixed (B, X*) pairs."""
     torch = _torch()
-    smp = Sampler(n, m, lam)
-    net = WarmStart(n, blocks, net_seed)
+    tot = torch.zeros(1, dtype=torch.float64, device="cuda")
+    li = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for B, T in pairs:
+        L.cta_ws_forward(net.handle, B, net._X0)
+        L.cta_ws_mse(net.handle, net._X0, T, net._dX0, li)
+        tot += li
+    return float(tot.item()) / max(1, len(pairs))
+
+
+def train(n, m, lam, samples, batch=4, blocks=5, lr=1e-3, seed0=0, target_rtol=1e-5,
+          log_every=100, log=print, net_seed=0, smp=None, net=None):
+    """Train a network (fresh unless given) on `samples` generated solves
+    (seeds seed0..); every sample is used once.  The logged loss is the mean
+    over the samples since the previous log line.  Returns the network, the
+    sampler and a training record."""
+    torch = _torch()
+    smp = smp or Sampler(n, m, lam)
+    net = net or WarmStart(n, blocks, net_seed)
     steps = samples // batch
     hist, t0 = [], time.time()
     solve_s = train_s = 0.0
     iters = []
+    net.loss.zero_()
+    since = 0
     for st in range(steps):
         net.zero_grad()
-        net.loss.zero_()
         for j in range(batch):
             seed = seed0 + st * batch + j
             ta = time.time()
@@ -155,9 +170,11 @@ def train(n, m, lam, samples, batch=4, blocks=5, lr=1e-3, seed0=0, target_rtol=1
             solve_s += tb - ta
             train_s += time.time() - tb
         net.step(lr_at(st, steps, lr))
-        if st % log_every == 0 or st == steps - 1:
-            torch.cuda.synchronize()
-            loss = float(net.loss.item()) / batch
+        since += batch
+        if (st + 1) % log_every == 0 or st == steps - 1:
+            loss = float(net.loss.item()) / since
+            net.loss.zero_()
+            since = 0
             hist.append((st, loss))
             log(f"step {st}/{steps} samples {(st + 1) * batch} loss {loss:.4e} "
                 f"target iters {np.mean(iters[-batch:]):.0f} elapsed {time.time() - t0:.0f}s")

@@ -24,11 +24,19 @@ def test_trained_start_saves_iterations():
     torch_cuda()
     from paper_1001_5460_amd import warmstart as ws
 
-    net, smp, rec = ws.train(N_SMALL, M_SMALL, 1e-3, samples=600, batch=4, blocks=2, lr=2e-3,
-                             log_every=50)
-    hist = [l for _, l in rec["loss_history"]]
-    print("loss history", hist)
-    assert hist[-1] < 0.5 * hist[0]
+    smp = ws.Sampler(N_SMALL, M_SMALL, 1e-3)
+    net = ws.WarmStart(N_SMALL, blocks=2, seed=0)
+    val = []
+    for seed in range(20000, 20008):  # validation seeds, outside training and test
+        B = smp.rhs(seed)
+        val.append((B, smp.target(B)[0]))
+    before = ws.validation_loss(net, smp, val)
+    net, smp, rec = ws.train(N_SMALL, M_SMALL, 1e-3, samples=600, batch=4, lr=2e-3, log_every=25,
+                             smp=smp, net=net)
+    after = ws.validation_loss(net, smp, val)
+    print("loss history", [round(l, 5) for _, l in rec["loss_history"]])
+    print(f"validation loss {before:.4e} -> {after:.4e}")
+    assert after < 0.5 * before
     rows, kept = ws.evaluate(net, smp, range(10000, 10012), rtol=1e-8, keep=2)
     s = ws.summarize(rows)
     print(s)
