@@ -37,6 +37,8 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # copy-kernel calibration of the rocprofv3 FETCH_SIZE / WRITE_SIZE counters and the
 # traffic of the dominant kernel, both from profiles/ (None until measured)
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_normal_last_bf16_128x128x96x24.json")
+# trained warm-start network of the 64x64x64x16 blob workload
+WS_CKPT = os.path.join(HERE, "paper_1001_5460_amd", "weights", "ws_64x64x64x16.npz")
 
 
 def chain_flops_rect(in_ext, out_ext):
@@ -179,6 +181,96 @@ def run_batched(args, cta, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_warmstart(args, cta, torch, seeds, reps=5):
+    """Learned warm start on the 64x64x64x16 blob workload (held-out seeds):
+    network inference time with its per-kernel breakdown, the convolution's
+    roofline, one training step's time, and the gain of CG from the network's
+    start over CG from zero (iterations and time to 1e-8, inference included)."""
+    import workload
+    from paper_1001_5460_amd import warmstart as ws
+    cfg = workload.CONFIGS[4]
+    n, m = cfg["n"], cfg["m"]
+    V = int(np.prod(n))
+    trained = os.path.exists(WS_CKPT)
+    if trained:
+        net, meta = ws.WarmStart.load(WS_CKPT)
+    else:
+        net, meta = ws.WarmStart(n, 5, 0), {}
+    smp = ws.Sampler(n, m, cfg["lam"])
+    smp.op.tune("bf16", reps=3)
+    smp.op.tune("f64", reps=3)
+    B = smp.rhs(seeds[0])
+    X0 = torch.empty_like(B)
+    for _ in range(2):
+        net(B, X0)
+    torch.cuda.synchronize()
+    cta.cta_prof_reset()
+    cta.cta_prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net(B, X0)
+    torch.cuda.synchronize()
+    fwd_s = (time.perf_counter() - t0) / reps
+    cta.cta_prof_enable(False)
+    prof = cta.cta_prof_read()
+    cta.cta_prof_reset()
+    # bytes per voxel of one launch of each convolution form: 64 in + 64 out (+ 64 aux)
+    conv_bytes = {"relu": 128, "res": 192, "mask": 192, "add": 192}
+    kernels = {}
+    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
+        avg = v["total_ms"] / v["count"]
+        e = {"count": v["count"], "avg_ms": round(avg, 4)}
+        if k.startswith("ws_conv."):
+            e["GB/s"] = round(V * conv_bytes[k.split(".")[-1]] / (avg / 1e3) / 1e9, 1)
+            e["TFLOP/s"] = round(2 * V * 32 * 32 * 5 / (avg / 1e3) / 1e12, 2)
+        kernels[k] = e
+    convs = [k for k in prof if k.startswith("ws_conv.")]
+    dom = max(convs, key=lambda k: prof[k]["total_ms"])
+    avg_s = prof[dom]["total_ms"] / prof[dom]["count"] / 1e3
+    alg = V * conv_bytes[dom.split(".")[-1]]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(alg / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(avg_s * 1e3, 4),
+            "launches": prof[dom]["count"]}
+    rows = ws.evaluate(net, smp, seeds, rtol=cfg["rtol"], log=lambda *a: None)
+    summ = ws.summarize(rows)
+    # one training step (forward, loss, backward, Adam) on a copy of the network
+    net2 = ws.WarmStart(n, net.blocks, 1, params=net.params())
+    T, _ = smp.target(B)
+    net2.zero_grad()
+    net2.accumulate(B, T)
+    net2.step(1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net2.zero_grad()
+        net2.accumulate(B, T)
+        net2.step(1e-4)
+    torch.cuda.synchronize()
+    train_s = (time.perf_counter() - t0) / reps
+    net2.close()
+    out = {
+        "workload": "warmstart_64x64x64x16_blobs_to_1e-8",
+        "network": {"blocks": net.blocks, "channels": 32, "width": 5,
+                    "parameters": int(cta.cta_ws_num_params(net.handle)), "trained": trained,
+                    "training_samples": meta.get("samples")},
+        "held_out_seeds": [seeds[0], seeds[-1]],
+        "zero_start": {"iters_mean": summ["zero_iters_mean"], "s_mean": round(summ["zero_s_mean"], 5)},
+        "warm_start": {"iters_mean": summ["warm_iters_mean"], "s_mean": round(summ["warm_s_mean"], 5),
+                       "start_rel_res_median": summ["start_res_median"]},
+        "iters_saved_frac": round(summ["iters_saved_frac"], 4),
+        "time_speedup": round(summ["time_speedup"], 4),
+        "all_converged": summ["all_converged"],
+        "inference_ms": round(fwd_s * 1e3, 3),
+        "train_step_ms": round(train_s * 1e3, 3),
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    net.close()
+    smp.op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,9 +280,14 @@ def main():
     ap.add_argument("--max-inner", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--workload", choices=["headline", "batched"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "batched", "warmstart"], default="headline",
                     help="headline: the 128x128x96x24 solve (default); batched: 256 uneven "
-                         "3-D problems in one persistent launch vs the sequential loop")
+                         "3-D problems in one persistent launch vs the sequential loop; "
+                         "warmstart: the learned warm start on 64x64x64x16 blob problems")
+    ap.add_argument("--ws-seeds", type=int, default=8,
+                    help="held-out seeds (from 10000) of the warm-start gain measurement")
+    ap.add_argument("--no-warmstart", action="store_true",
+                    help="skip the warm-start summary in the headline line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the library's plain copy kernel (FP32, one 128x128x96x24 "
                          "tensor, 5 launches) for counter calibration, then exit")
@@ -221,6 +318,15 @@ def main():
 
     if args.workload == "batched":
         run_batched(args, cta, torch)
+        return
+    if args.workload == "warmstart":
+        ws = run_warmstart(args, cta, torch, list(range(10000, 10000 + args.ws_seeds)))
+        out = {"metric": "time to 1e-8 residual from the learned warm start, 64x64x64x16 blob problems",
+               "value": ws["warm_start"]["s_mean"], "unit": "s per solve (inference included)",
+               "higher_is_better": False, "n_gpus": 1, "steps": args.ws_seeds, "dtype": "bf16",
+               "data": "synthetic", "config": {"workload": ws["workload"]},
+               "vs_zero_start": ws["time_speedup"], "roofline": ws["roofline"], "warm_start": ws}
+        print(json.dumps(out), flush=True)
         return
 
     p = workload.config_problem(2)
@@ -354,6 +460,14 @@ def main():
             cmp[f"{tol:g}"] = {"seconds": round(dt, 4), "iters": info["iters"], "status": info["status"],
                                "rel_res_true": info["rel_res_true"],
                                "iters_per_s": round(info["iters"] / dt, 2)}
+        # plain FP64 CG to 1e-8 (FP64 chain, FP64 vectors)
+        X64 = torch.empty(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info64 = op.solve(B, X64, precision="f64", rtol=1e-8, max_iter=3000, check_every=16)
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t
+        del X64
         # mixed precision to 1e-6 for a like-for-like time comparison
         X6 = torch.empty(n, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
@@ -369,7 +483,14 @@ def main():
             "speedup_vs_fp32_at_1e-8": (round(cmp["1e-08"]["seconds"] / out["time_to_1e-8_s"], 3)
                                         if cmp["1e-08"]["status"] == 0 else None),
             "fp32_reaches_1e-8": cmp["1e-08"]["status"] == 0,
+            "fp64_cg_1e-8": {"seconds": round(dt64, 4), "iters": info64["iters"],
+                             "status": info64["status"], "rel_res_true": info64["rel_res_true"]},
+            "speedup_vs_fp64_at_1e-8": round(dt64 / out["time_to_1e-8_s"], 3),
         }
+
+    if not args.no_warmstart:
+        # the learned warm start on its own workload (held-out seeds), outside the timed region
+        out["warm_start"] = run_warmstart(args, cta, torch, list(range(10000, 10000 + args.ws_seeds)))
 
     if not args.no_cpu_baseline:
         base, judge = cpu_baseline(p, X.cpu().numpy())

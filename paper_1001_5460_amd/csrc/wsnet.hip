@@ -120,6 +120,91 @@ __global__ __launch_bounds__(CTA_WG) void k_conv(const bf16* __restrict__ in,
     }
 }
 
+// Column form of the same convolution, for modes whose stride sk is at least
+// 16: a wave owns 16 consecutive trailing indices t of one leading index and
+// walks i = 0..nk-1 along the mode, keeping the five input rows of the stencil
+// (positions i-2..i+2) in registers and the next two prefetched, so every
+// input row is read from memory once.  Same arithmetic as k_conv (same taps,
+// same order of the MFMA sums), so the two forms give identical results.
+template <int EPI>
+__global__ __launch_bounds__(CTA_WG) void k_conv_col(const bf16* __restrict__ in,
+                                                     const bf16* __restrict__ Wr,
+                                                     const float* __restrict__ bias, const bf16* aux,
+                                                     bf16* out, int nk, int sk, int tb, int64_t ncols) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, l16 = lane & 15;
+    bf16x8 wf[WID][2];
+#pragma unroll
+    for (int w = 0; w < WID; ++w)
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+            wf[w][rt] = *reinterpret_cast<const bf16x8*>(Wr + ((w * C) + rt * 16 + l16) * C + 8 * g);
+    float bv[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            bv[rt][r] = (EPI == EPI_RELU || EPI == EPI_RES) ? bias[rt * 16 + 4 * g + r] : 0.f;
+    for (int64_t col = (int64_t)blockIdx.x * CTA_WAVES + wave; col < ncols;
+         col += (int64_t)gridDim.x * CTA_WAVES) {
+        const int64_t li = col / tb;
+        const int t = (int)(col - li * tb) * 16 + l16;
+        const bool ok = t < sk;
+        const int64_t base = li * nk * (int64_t)sk + t;  // voxel (li, 0, t)
+        auto ld = [&](int i) -> bf16x8 {
+            return (ok && i < nk) ? *reinterpret_cast<const bf16x8*>(in + (base + (int64_t)i * sk) * C + 8 * g)
+                                  : zero8();
+        };
+        bf16x8 r0 = zero8(), r1 = zero8(), r2 = ld(0), r3 = ld(1), r4 = ld(2), p0 = ld(3), p1 = ld(4);
+        for (int i = 0; i < nk; ++i) {
+            const int64_t vox = base + (int64_t)i * sk;
+            bf16x4 a4[2];
+            if constexpr (EPI != EPI_RELU) {
+                if (ok) {
+                    a4[0] = *reinterpret_cast<const bf16x4*>(aux + vox * C + 4 * g);
+                    a4[1] = *reinterpret_cast<const bf16x4*>(aux + vox * C + 16 + 4 * g);
+                }
+            }
+            floatx4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            const bf16x8 rw[WID] = {r0, r1, r2, r3, r4};
+#pragma unroll
+            for (int w = 0; w < WID; ++w) {
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[w][0], rw[w], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[w][1], rw[w], acc[1], 0, 0, 0);
+            }
+            r0 = r1;
+            r1 = r2;
+            r2 = r3;
+            r3 = r4;
+            r4 = p0;
+            p0 = p1;
+            p1 = ld(i + 5);
+            if (!ok) continue;
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                float y[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) y[r] = acc[rt][r] + bv[rt][r];
+                if constexpr (EPI != EPI_RELU) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float av = (float)a4[rt][r];
+                        if constexpr (EPI == EPI_MASK) y[r] = av > 0.f ? y[r] : 0.f;
+                        else y[r] += av;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) y[r] = fmaxf(y[r], 0.f);
+                }
+                bf16x4 o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = (bf16)y[r];
+                *reinterpret_cast<bf16x4*>(out + vox * C + rt * 16 + 4 * g) = o;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ weight gradient
 constexpr int WCH = 64;        // voxels per chunk
 constexpr int WLD = WCH + 8;   // LDS row pitch (bf16)
@@ -508,17 +593,37 @@ extern "C" cta_status cta_ws_destroy(cta_ws w) {
 
 extern "C" int64_t cta_ws_num_params(cta_ws w) { return w ? w->P : 0; }
 
+// tracer names per epilogue: [EPI][flat, column]
+static const char* const kConvName[4][2] = {{"ws_conv.flat.relu", "ws_conv.col.relu"},
+                                            {"ws_conv.flat.res", "ws_conv.col.res"},
+                                            {"ws_conv.flat.mask", "ws_conv.col.mask"},
+                                            {"ws_conv.flat.add", "ws_conv.col.add"}};
+
+template <int EPI>
+static void conv_go(cta_ws_s* w, const bf16* in, const bf16* Wr, const float* bias, const bf16* aux,
+                    bf16* out, int nk, int sk, hipStream_t s) {
+    if (sk >= 16) {
+        const int tb = (sk + 15) / 16;
+        const int64_t ncols = (int64_t)(w->V / ((int64_t)nk * sk)) * tb;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((ncols + CTA_WAVES - 1) / CTA_WAVES, 65536));
+        ProfScope ps(kConvName[EPI][1], s);
+        k_conv_col<EPI><<<grid, CTA_WG, 0, s>>>(in, Wr, bias, aux, out, nk, sk, tb, ncols);
+    } else {
+        ProfScope ps(kConvName[EPI][0], s);
+        k_conv<EPI><<<w->conv_grid, CTA_WG, 0, s>>>(in, Wr, bias, aux, out, w->V, nk, sk);
+    }
+}
+
 static cta_status conv_launch(cta_ws_s* w, int epi, const bf16* in, const bf16* Wr, const float* bias,
                               const bf16* aux, bf16* out, int k, hipStream_t s) {
     int sk = 1;
     for (int l = k + 1; l < 4; ++l) sk *= (int)w->n[l];
     const int nk = (int)w->n[k];
-    const int g = w->conv_grid;
     switch (epi) {
-        case EPI_RELU: k_conv<EPI_RELU><<<g, CTA_WG, 0, s>>>(in, Wr, bias, aux, out, w->V, nk, sk); break;
-        case EPI_RES: k_conv<EPI_RES><<<g, CTA_WG, 0, s>>>(in, Wr, bias, aux, out, w->V, nk, sk); break;
-        case EPI_MASK: k_conv<EPI_MASK><<<g, CTA_WG, 0, s>>>(in, Wr, bias, aux, out, w->V, nk, sk); break;
-        default: k_conv<EPI_ADD><<<g, CTA_WG, 0, s>>>(in, Wr, bias, aux, out, w->V, nk, sk); break;
+        case EPI_RELU: conv_go<EPI_RELU>(w, in, Wr, bias, aux, out, nk, sk, s); break;
+        case EPI_RES: conv_go<EPI_RES>(w, in, Wr, bias, aux, out, nk, sk, s); break;
+        case EPI_MASK: conv_go<EPI_MASK>(w, in, Wr, bias, aux, out, nk, sk, s); break;
+        default: conv_go<EPI_ADD>(w, in, Wr, bias, aux, out, nk, sk, s); break;
     }
     WS_HIP(hipGetLastError());
     return CTA_OK;
@@ -528,10 +633,12 @@ extern "C" cta_status cta_ws_forward(cta_ws w, const void* B, void* X0, int trai
     (void)training;  // activations are always kept: the memory is allocated at creation
     if (!w || !B || !X0) return fail(CTA_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    ProfScope ps("ws_forward", s);
     WS_HIP(launch_dot(DT_F32, B, B, w->V, w->dpart, w->scal, w->ss, s));
     const float* P = w->params;
-    k_lift<<<w->pw_grid, CTA_WG, 0, s>>>((const float*)B, w->ss, w->V, P, P + C, w->bhat, w->h[0]);
+    {
+        ProfScope ps("ws_lift", s);
+        k_lift<<<w->pw_grid, CTA_WG, 0, s>>>((const float*)B, w->ss, w->V, P, P + C, w->bhat, w->h[0]);
+    }
     WS_HIP(hipGetLastError());
     for (int b = 0; b < w->blocks; ++b) {
         const bf16* hin = w->h[b];
@@ -547,7 +654,10 @@ extern "C" cta_status cta_ws_forward(cta_ws w, const void* B, void* X0, int trai
         if (st != CTA_OK) return st;
     }
     const int64_t op = off_pw(w->blocks);
-    k_proj<<<w->pw_grid, CTA_WG, 0, s>>>(w->h[w->blocks], P + op, P + op + C, w->ss, w->V, (float*)X0);
+    {
+        ProfScope ps("ws_proj", s);
+        k_proj<<<w->pw_grid, CTA_WG, 0, s>>>(w->h[w->blocks], P + op, P + op + C, w->ss, w->V, (float*)X0);
+    }
     WS_HIP(hipGetLastError());
     return CTA_OK;
 }
@@ -557,7 +667,10 @@ extern "C" cta_status cta_ws_mse(cta_ws w, const void* X0, const void* T, void* 
     if (!w || !X0 || !T || !dX0) return fail(CTA_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     const int g = std::min(w->pw_grid, kMaxGrid);
-    k_mse<<<g, CTA_WG, 0, s>>>((const float*)X0, (const float*)T, w->ss, w->V, (float*)dX0, w->dpart);
+    {
+        ProfScope ps("ws_mse", s);
+        k_mse<<<g, CTA_WG, 0, s>>>((const float*)X0, (const float*)T, w->ss, w->V, (float*)dX0, w->dpart);
+    }
     WS_HIP(hipGetLastError());
     if (loss) {
         // mean = total / V: the finalize writes the total; scale on the device
@@ -571,8 +684,12 @@ static cta_status wgrad_launch(cta_ws_s* w, const bf16* g, const bf16* x, int k,
                                hipStream_t s) {
     int sk = 1;
     for (int l = k + 1; l < 4; ++l) sk *= (int)w->n[l];
-    k_wgrad<<<w->wg_grid, CTA_WG, 0, s>>>(g, x, w->V, (int)w->n[k], sk, w->part);
+    {
+        ProfScope ps("ws_wgrad", s);
+        k_wgrad<<<w->wg_grid, CTA_WG, 0, s>>>(g, x, w->V, (int)w->n[k], sk, w->part);
+    }
     WS_HIP(hipGetLastError());
+    ProfScope ps("ws_reduce", s);
     k_reduce_add<<<(NCONV + CTA_WG - 1) / CTA_WG, CTA_WG, 0, s>>>(w->part, w->wg_grid, NCONV, WG_PART, grad_conv);
     WS_HIP(hipGetLastError());
     return CTA_OK;
@@ -581,11 +698,13 @@ static cta_status wgrad_launch(cta_ws_s* w, const bf16* g, const bf16* x, int k,
 extern "C" cta_status cta_ws_backward(cta_ws w, const void* dX0, void* stream) {
     if (!w || !dX0) return fail(CTA_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    ProfScope ps("ws_backward", s);
     const float* P = w->params;
     const int64_t op = off_pw(w->blocks);
     bf16* dh = w->G[0];
-    k_proj_bwd<<<w->pw_grid, CTA_WG, 0, s>>>((const float*)dX0, w->ss, w->h[w->blocks], P + op, w->V, dh, w->part);
+    {
+        ProfScope ps("ws_proj_bwd", s);
+        k_proj_bwd<<<w->pw_grid, CTA_WG, 0, s>>>((const float*)dX0, w->ss, w->h[w->blocks], P + op, w->V, dh, w->part);
+    }
     WS_HIP(hipGetLastError());
     k_reduce_add<<<1, CTA_WG, 0, s>>>(w->part, w->pw_grid, C + 1, C + 1, w->grad + op);
     WS_HIP(hipGetLastError());
@@ -608,7 +727,10 @@ extern "C" cta_status cta_ws_backward(cta_ws w, const void* dX0, void* stream) {
         if (st == CTA_OK) st = conv_launch(w, EPI_ADD, w->G[1], Wb, nullptr, dh, dh, 0, s);
         if (st != CTA_OK) return st;
     }
-    k_lift_bwd<<<w->pw_grid, CTA_WG, 0, s>>>(dh, w->bhat, w->V, w->part);
+    {
+        ProfScope ps("ws_lift_bwd", s);
+        k_lift_bwd<<<w->pw_grid, CTA_WG, 0, s>>>(dh, w->bhat, w->V, w->part);
+    }
     WS_HIP(hipGetLastError());
     k_reduce_add<<<1, CTA_WG, 0, s>>>(w->part, w->pw_grid, C, 2 * C, w->grad);
     WS_HIP(hipGetLastError());
@@ -630,8 +752,11 @@ extern "C" cta_status cta_ws_adam_step(cta_ws w, float lr, float beta1, float be
     w->step += 1;
     const float bc1 = (float)(1.0 - std::pow((double)beta1, w->step));
     const float bc2 = (float)(1.0 - std::pow((double)beta2, w->step));
-    k_adam<<<(int)((w->P + CTA_WG - 1) / CTA_WG), CTA_WG, 0, s>>>(w->params, w->grad, w->m, w->v, (int)w->P,
+    {
+        ProfScope ps("ws_adam", s);
+        k_adam<<<(int)((w->P + CTA_WG - 1) / CTA_WG), CTA_WG, 0, s>>>(w->params, w->grad, w->m, w->v, (int)w->P,
                                                                  lr, beta1, beta2, eps, bc1, bc2);
+    }
     WS_HIP(hipGetLastError());
     return ws_refresh(w, s);
 }
