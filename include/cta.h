@@ -63,12 +63,21 @@ typedef enum { CTA_F64 = 0, CTA_F32 = 1, CTA_BF16 = 2 } cta_dtype;
  *                      BF16 (nearest-even), BF16 MFMA with FP32 accumulation;
  *                      regulariser in FP32; FP64 dots.
  *  CTA_PREC_BF16_REFINE  (solves only) FP64 outer iterative refinement with an
- *                      FP64 residual recomputation, inner CG in CTA_PREC_BF16. */
+ *                      FP64 residual recomputation, inner CG in CTA_PREC_BF16
+ *                      restarted from zero at every outer step.
+ *  CTA_PREC_BF16_RELIABLE  (solves only) one CG in CTA_PREC_BF16 with reliable
+ *                      updates: whenever the recursive residual has dropped by
+ *                      inner_rtol since the last update, the FP32 correction is
+ *                      added to the FP64 solution, the residual is replaced by
+ *                      the FP64 true residual and the iteration continues with
+ *                      the same search direction (beta rescaled by
+ *                      rho_true / rho_recursive). */
 typedef enum {
     CTA_PREC_F64 = 0,
     CTA_PREC_F32 = 1,
     CTA_PREC_BF16 = 2,
-    CTA_PREC_BF16_REFINE = 3
+    CTA_PREC_BF16_REFINE = 3,
+    CTA_PREC_BF16_RELIABLE = 4
 } cta_precision;
 
 /* Largest extent of any mode (rows or columns of any factor). */
@@ -170,6 +179,10 @@ cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_var
  *   CTA_PREC_BF16         B, X F32  (inner arithmetic only; rarely reaches 1e-8)
  *   CTA_PREC_BF16_REFINE  B, X F64  (outer FP64 refinement to rtol, inner CG
  *                                    in CTA_PREC_BF16 to inner_rtol)
+ *   CTA_PREC_BF16_RELIABLE B, X F64 (BF16-chain CG with FP64 reliable updates
+ *                                    every inner_rtol reduction; max_refine
+ *                                    bounds the updates, max_iter the
+ *                                    iterations between two updates)
  * X is read as the starting tensor when x0_given != 0, else overwritten.
  * With fallback_zero != 0 a starting tensor whose residual is not smaller than
  * ||B|| is replaced by zero.  The call synchronises `stream` and fills
@@ -190,7 +203,7 @@ typedef struct {
 typedef struct {
     int status;               /* cta_status of this solve */
     int iters;                /* total CG iterations (all inner solves) */
-    int refine_steps;         /* outer refinement steps (0 without refinement) */
+    int refine_steps;         /* outer refinement steps or reliable updates (0 without) */
     double rel_res_recursive; /* ||r_rec|| / ||B|| at exit */
     double rel_res_true;      /* ||B - N(X)|| / ||B|| recomputed in FP64 */
     double seconds;           /* wall time of the solve (host clock) */

@@ -19,11 +19,12 @@ _LIB = None
 CTA_OK = 0
 CTA_NOT_CONVERGED = 1
 F64, F32, BF16 = 0, 1, 2
-PREC_F64, PREC_F32, PREC_BF16, PREC_BF16_REFINE = 0, 1, 2, 3
+PREC_F64, PREC_F32, PREC_BF16, PREC_BF16_REFINE, PREC_BF16_RELIABLE = 0, 1, 2, 3, 4
 _STATUS = {0: "CTA_OK", 1: "CTA_NOT_CONVERGED", -1: "CTA_ERR_ARG", -2: "CTA_ERR_SHAPE",
            -3: "CTA_ERR_DTYPE", -4: "CTA_ERR_HIP", -5: "CTA_ERR_NOMEM",
            -6: "CTA_ERR_BREAKDOWN", -7: "CTA_ERR_UNSUPPORTED"}
-_PREC = {"f64": PREC_F64, "f32": PREC_F32, "bf16": PREC_BF16, "bf16_refine": PREC_BF16_REFINE}
+_PREC = {"f64": PREC_F64, "f32": PREC_F32, "bf16": PREC_BF16, "bf16_refine": PREC_BF16_REFINE,
+         "bf16_reliable": PREC_BF16_RELIABLE}
 
 
 class CtaError(RuntimeError):
@@ -323,7 +324,7 @@ def _info_dict(info):
 
 
 def cta_cg_solve(h, B, X, stream=None, **opts):
-    """Solve N(X) = B; options as in cta_cg_opts (precision may be 'f64', 'f32', 'bf16', 'bf16_refine')."""
+    """Solve N(X) = B; options as in cta_cg_opts (precision may be 'f64', 'f32', 'bf16', 'bf16_refine', 'bf16_reliable')."""
     o = _opts(**opts)
     info = _CgInfo()
     st = load_library().cta_cg_solve(h, _dev(B, "B"), _dev(X, "X"), _dt(B), ctypes.byref(o),

@@ -535,20 +535,21 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
     const int prec = opts->precision;
-    if (prec < CTA_PREC_F64 || prec > CTA_PREC_BF16_REFINE) return fail(CTA_ERR_ARG, "bad precision");
+    if (prec < CTA_PREC_F64 || prec > CTA_PREC_BF16_RELIABLE) return fail(CTA_ERR_ARG, "bad precision");
+    const bool mixed = prec == CTA_PREC_BF16_REFINE || prec == CTA_PREC_BF16_RELIABLE;
     if (!(opts->rtol >= 0) || opts->max_iter < 0) return fail(CTA_ERR_ARG, "bad rtol or max_iter");
-    const int want = (prec == CTA_PREC_F64 || prec == CTA_PREC_BF16_REFINE) ? DT_F64 : DT_F32;
+    const int want = (prec == CTA_PREC_F64 || mixed) ? DT_F64 : DT_F32;
     if ((int)dtype != want)
         return fail(CTA_ERR_DTYPE, "B and X must be %s for this precision", want == DT_F64 ? "CTA_F64" : "CTA_F32");
     if (B == X) return fail(CTA_ERR_ARG, "B and X must not overlap");
     const int N = op->order;
-    if (!tail_fits(prec_tc(prec == CTA_PREC_BF16_REFINE ? CTA_PREC_F64 : prec), (int)op->n[N - 2], (int)op->n[N - 1]))
+    if (!tail_fits(prec_tc(mixed ? CTA_PREC_F64 : prec), (int)op->n[N - 2], (int)op->n[N - 1]))
         return fail(CTA_ERR_UNSUPPORTED, "last two extents too large for the fused tail in this precision");
     const int check = opts->check_every > 0 ? opts->check_every : 16;
     const int64_t n = op->N;
     int done = 0, iters = 0;
 
-    if (prec != CTA_PREC_BF16_REFINE) {
+    if (!mixed) {
         const int tv = prec_tvec(prec);
         const size_t vb = (size_t)n * dt_size(tv);
         CTA_HIP(launch_dot(tv, B, B, n, op->partials, op->scal, &op->scal->bnorm2, s));
@@ -619,7 +620,61 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
         }
         int steps = 0, total = 0;
         done = DONE_RUNNING;
-        while (true) {
+        if (prec == CTA_PREC_BF16_RELIABLE) {
+            // One CG over the BF16 chain; vx holds the FP32 correction since the
+            // last reliable update, vp the search direction kept across updates.
+            const double target = rtol * rtol * bn2;
+            CTA_HIP(launch_fill_zero(op->vx, (size_t)n * 4, s));
+            CTA_HIP(launch_fill_zero(op->vp, (size_t)n * 4, s));
+            while (true) {
+                if (!std::isfinite(rr)) {
+                    done = DONE_BREAKDOWN;
+                    break;
+                }
+                if (rr <= target) {
+                    done = DONE_CONVERGED;
+                    break;
+                }
+                if (steps >= opts->max_refine) {
+                    done = DONE_MAXITER;
+                    break;
+                }
+                // iterate until the recursive residual has dropped by eta since this
+                // update (or a little below the target, which the true residual then checks)
+                const double thr = std::max(eta * eta * rr, 0.25 * target);
+                CTA_HIP(launch_cg_group(op->scal, thr, opts->max_iter, steps > 0 ? 1 : 0, s));
+                int gdone = DONE_RUNNING;
+                for (;;) {
+                    for (int c = 0; c < check; ++c) {
+                        CTA_TRY(apply_normal(op, nullptr, op->vq, CTA_PREC_BF16, POST_ALPHA, nullptr, true, s));
+                        CTA_HIP(launch_cg_update(DT_F32, op->vx, op->vr, op->vp, op->vq, n, op->partials,
+                                                 op->scal, s));
+                    }
+                    CTA_TRY(read_scal(op, s));
+                    gdone = op->hscal->done;
+                    if (gdone != DONE_RUNNING) break;
+                }
+                total += op->hscal->iters;
+                if (gdone == DONE_BREAKDOWN && op->hscal->iters == 0) {
+                    done = DONE_BREAKDOWN;
+                    break;
+                }
+                // reliable update: X64 += vx, vx = 0, r = B - N64(X64)
+                CTA_HIP(launch_add_f64((double*)X, op->vx, DT_F32, n, s));
+                CTA_HIP(launch_fill_zero(op->vx, (size_t)n * 4, s));
+                ++steps;
+                CTA_TRY(apply_normal(op, X, op->vq, CTA_PREC_F64, POST_NONE, nullptr, false, s));
+                CTA_HIP(launch_residual(DT_F64, DT_F32, B, op->vq, op->vr, n, op->partials, op->scal,
+                                        &op->scal->dot, s));
+                CTA_TRY(read_scal(op, s));
+                rr = op->hscal->dot;
+                if (gdone == DONE_BREAKDOWN) {
+                    done = rr <= target ? DONE_CONVERGED : DONE_BREAKDOWN;
+                    break;
+                }
+            }
+        }
+        while (prec == CTA_PREC_BF16_REFINE) {
             if (!std::isfinite(rr)) {
                 done = DONE_BREAKDOWN;
                 break;

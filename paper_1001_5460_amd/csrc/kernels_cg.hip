@@ -322,6 +322,40 @@ __global__ void k_cg_setup(CgScalars* scal, double rtol2, int max_iter) {
         scal->done = DONE_RUNNING;
 }
 
+// Start of a group of CG iterations.  keep_dir = 0: a fresh start from the
+// residual whose <r, r> is in scal->rho (beta = 0, the search direction is
+// rebuilt from r).  keep_dir = 1: after a reliable update, the true
+// residual's <r, r> is in scal->dot; the search direction is kept and
+// beta = rho_true / rho_k, where rho_k = rho / beta is the residual norm
+// before the last CG step.
+__global__ void k_cg_group(CgScalars* scal, double threshold, int max_iter, int keep_dir) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double rt = keep_dir ? scal->dot : scal->rho;
+    double beta = 0.0;
+    if (keep_dir && scal->rho > 0.0) beta = scal->beta * rt / scal->rho;
+    scal->beta = beta;
+    scal->rho = rt;
+    scal->rho0 = rt;
+    scal->alpha = 0.0;
+    scal->threshold = threshold;
+    scal->iters = 0;
+    scal->max_iter = max_iter;
+    if (!__builtin_isfinite(rt) || !__builtin_isfinite(beta))
+        scal->done = DONE_BREAKDOWN;
+    else if (rt <= threshold)
+        scal->done = DONE_CONVERGED;
+    else if (max_iter <= 0)
+        scal->done = DONE_MAXITER;
+    else
+        scal->done = DONE_RUNNING;
+}
+
+hipError_t launch_cg_group(CgScalars* scal, double threshold, int max_iter, int keep_dir, hipStream_t s) {
+    ProfScope ps("cg_group", s);
+    k_cg_group<<<1, 64, 0, s>>>(scal, threshold, max_iter, keep_dir);
+    return hipGetLastError();
+}
+
 hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s) {
     ProfScope ps("cg_setup", s);
     k_cg_setup<<<1, 64, 0, s>>>(scal, rtol2, max_iter);

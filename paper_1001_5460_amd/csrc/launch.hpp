@@ -99,6 +99,9 @@ hipError_t launch_cg_update(int tv, void* x, void* r, const void* p, const void*
                             double* partials, CgScalars* scal, hipStream_t s);
 // CG setup from device dots: threshold, rho, beta = 0, done flag
 hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s);
+// start of an iteration group after a reliable update (true <r, r> in scal->dot)
+hipError_t launch_cg_group(CgScalars* scal, double threshold, int max_iter, int keep_dir,
+                           hipStream_t s);
 // padded copy of a (possibly transposed) device matrix in another dtype
 hipError_t launch_pad_matrix(int tin, int tout, const void* src, int rows, int cols, int trans,
                              void* dst, int rows_st, int ld, hipStream_t s);

@@ -187,7 +187,8 @@ def train(n, m, lam, samples, batch=4, blocks=5, lr=1e-3, seed0=0, target_rtol=1
     return net, smp, rec
 
 
-def evaluate(net, smp, seeds, rtol=1e-8, precision="bf16_refine", log=print, keep=0):
+def evaluate(net, smp, seeds, rtol=1e-8, precision="bf16_reliable", inner_rtol=0.1, log=print,
+             keep=0):
     """Solve each held-out seed's problem from zero and from the network's
     start (fallback to zero if the start is worse), to `rtol`; report
     iterations and wall time (network inference included for the warm start).
@@ -201,7 +202,8 @@ def evaluate(net, smp, seeds, rtol=1e-8, precision="bf16_refine", log=print, kee
         # zero start
         Xz = torch.zeros_like(B)
         t0 = time.perf_counter()
-        _, iz = smp.op.solve(B, Xz, precision=precision, rtol=rtol, max_iter=20000)
+        _, iz = smp.op.solve(B, Xz, precision=precision, rtol=rtol, max_iter=20000,
+                             inner_rtol=inner_rtol, max_refine=200)
         tz = time.perf_counter() - t0
         # warm start: network inference + solve
         torch.cuda.synchronize()
@@ -209,7 +211,7 @@ def evaluate(net, smp, seeds, rtol=1e-8, precision="bf16_refine", log=print, kee
         X0 = net(B32)
         Xw = X0.double()
         _, iw = smp.op.solve(B, Xw, precision=precision, rtol=rtol, max_iter=20000, x0_given=1,
-                             fallback_zero=1)
+                             fallback_zero=1, inner_rtol=inner_rtol, max_refine=200)
         tw = time.perf_counter() - t0
         # relative residual of the network's start alone
         r0 = _rel_res(smp.op, B, X0.double())

@@ -68,17 +68,42 @@ def test_config1_full_f32_judged():
     assert res <= p.rtol * 1.05, res
 
 
-def test_bf16_refine_small_reaches_1e8():
+@pytest.mark.parametrize("prec,eta", [("bf16_refine", 1e-2), ("bf16_reliable", 1e-1),
+                                      ("bf16_reliable", 1e-2)])
+def test_bf16_mixed_small_reaches_1e8(prec, eta):
+    """Both mixed-precision forms reach 1e-8, judged by the oracle's FP64 residual."""
     torch = torch_cuda()
     p = workload.config_problem(2, scale=8)
     ref, Y, B = _setup(p)
     op = cta.Operator(p.A, p.D, p.lam)
-    X, info = op.solve(dev(B, torch.float64), precision="bf16_refine", rtol=1e-8, max_iter=2000,
-                       inner_rtol=1e-2, max_refine=40)
+    X, info = op.solve(dev(B, torch.float64), precision=prec, rtol=1e-8, max_iter=2000,
+                       inner_rtol=eta, max_refine=60)
+    print(prec, eta, info)
     assert info["status"] == 0, info
     res = oracle.relative_residual(host(X), B, ref)
     assert res <= 1e-8 * 1.01, res
+    assert abs(info["rel_res_true"] - res) <= 1e-3 * res + 1e-12
     assert info["refine_steps"] >= 1
+
+
+def test_bf16_reliable_from_given_start_and_fallback():
+    torch = torch_cuda()
+    p = workload.config_problem(2, scale=8)
+    ref, Y, B = _setup(p)
+    op = cta.Operator(p.A, p.D, p.lam)
+    Bd = dev(B, torch.float64)
+    X0, _ = op.solve(Bd, precision="f64", rtol=1e-3, max_iter=2000)
+    X, info = op.solve(Bd, X0.clone(), precision="bf16_reliable", rtol=1e-8, max_iter=2000,
+                       inner_rtol=1e-1, max_refine=60, x0_given=1, fallback_zero=1)
+    Xz, infoz = op.solve(Bd, precision="bf16_reliable", rtol=1e-8, max_iter=2000, inner_rtol=1e-1,
+                         max_refine=60)
+    assert info["status"] == 0 and infoz["status"] == 0
+    assert info["iters"] < infoz["iters"]
+    Xb, infob = op.solve(Bd, torch.full_like(Bd, 1e3), precision="bf16_reliable", rtol=1e-8,
+                         max_iter=2000, inner_rtol=1e-1, max_refine=60, x0_given=1, fallback_zero=1)
+    assert infob["iters"] == infoz["iters"] and torch.equal(Xb, Xz)
+    for Xs in (X, Xz):
+        assert oracle.relative_residual(host(Xs), B, ref) <= 1e-8 * 1.01
 
 
 def test_f64_and_f32_agree_with_dense_solution_tiny():
