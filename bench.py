@@ -4,10 +4,11 @@
 lambda = 1e-4) solved to 1e-8 relative residual on one MI355X.
 
 One step = one pass of the whole hot path over one input tensor Y already in
-HBM: the right-hand side B = Y x_k A_k^T (FP64 chain), then FP64 iterative
-refinement whose inner tensor CG (Fig. Tensor_CG) applies the normal operator
-as a BF16 MFMA chain of mode products with FP32 vectors and FP64 dots, with
-FP64 residual recomputation on the GPU, until ||B - N(X)|| <= 1e-8 ||B||.
+HBM: the right-hand side B = Y x_k A_k^T (FP64 chain), then the tensor CG
+(Fig. Tensor_CG) applying the normal operator as a BF16 MFMA chain of mode
+products with FP32 vectors and FP64 dots, whose residual is recomputed in
+FP64 on the GPU (reliable updates, or restarted refinement with
+--precision bf16_refine) until ||B - N(X)|| <= 1e-8 ||B||.
 
 Printed: one JSON line.  `value` = CG iterations per second over the timed
 steps (all inner iterations of the refinement); also the time to 1e-8, the
@@ -443,7 +444,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "bf16",
-        "precision": "BF16 MFMA chain (FP32 accumulate, FP32 vectors, FP64 dots) inside FP64 iterative refinement",
+        "precision": ("BF16 MFMA chain (FP32 accumulate, FP32 vectors, FP64 dots), "
+                      + ("FP64 reliable updates of the residual" if args.precision == "bf16_reliable"
+                         else "inside FP64 iterative refinement")),
         "data": "synthetic",
         "config": {"workload": "4d_128x128x96x24_bf16_chain_fp64_updates_to_1e-8", "unknowns": N,
                    "samples": int(np.prod(p.m)), "lambda": p.lam, "rtol": 1e-8,
