@@ -66,12 +66,16 @@ def algorithmic(name, N, n):
     """
     sn = sum(n)
     table = {
-        # BF16 inner CG: p = r + beta p fused into the tail (reads r, p; writes p, T1 bf16)
-        "tail_p.bf16": (N * (4 + 4 + 4 + 2), 2 * N * (n[2] + n[3])),
+        # BF16 inner CG: the previous step's x += alpha p and p = r + beta p fused into
+        # the tail (reads r, p, x; writes p, x, T1 bf16)
+        "tail_p.bf16": (N * (4 + 4 + 4 + 4 + 4 + 2), 2 * N * (n[2] + n[3])),
         "strided.bf16": (N * (2 + 2), 2 * N * n[1]),
         # reads T (bf16) and P (f32), writes Q (f32); banded regulariser + <P,Q>
         "normal_last.bf16": (N * (2 + 4 + 4), 2 * N * n[0]),
         "cg_update.f32": (N * (4 * 4 + 2 * 4), 0),
+        # r -= alpha q and <r, r> (x is updated by the next tail pass)
+        "cg_update_r.f32": (N * (4 + 4 + 4), 0),
+        "x_flush": (N * (4 + 4 + 4), 0),
         "tail.f64": (N * (8 + 8), 2 * N * (n[2] + n[3])),
         "strided.f64": (N * (8 + 8), 2 * N * n[1]),
         "normal_last.f64": (N * (8 + 8 + 8), 2 * N * n[0]),

@@ -162,7 +162,9 @@ cta_status cta_apply_normal_op(cta_op op, const void* P, void* Q, cta_dtype dtyp
  * in the handle for later applies and solves.  Synchronous. */
 cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
 /* The variants chosen for `chain` (tail, middle, last pass) into host_variants3;
- * cta_op_set_tuning sets them (each 0 or 1). */
+ * cta_op_set_tuning sets them: tail and middle 0 or 1 (tile shape), last
+ * 0..3 (0, 1: tile shape; 2, 3: the narrow shape with its tiles walked
+ * along the second mode first, in groups of 8 planes or all planes). */
 cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3);
 cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3);
 

@@ -46,6 +46,9 @@ struct cta_op_s {
 
 namespace cta {
 cta_status fail(cta_status st, const char* fmt, ...);
+// Q = N(P).  fuse_update: the chain input is p = r + beta p (op->vr, op->vp),
+// and with xsol the previous CG step's xsol += alpha p is applied on the
+// same pass.
 cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post, double* dot_out,
-                        bool fuse_update, hipStream_t s);
+                        bool fuse_update, hipStream_t s, void* xsol = nullptr);
 }  // namespace cta

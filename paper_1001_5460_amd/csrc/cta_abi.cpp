@@ -113,7 +113,7 @@ static int prec_tvec(int prec) { return prec == CTA_PREC_F64 ? DT_F64 : DT_F32; 
 //   middle: strided passes on modes N-3 .. 1
 //   last  : mode 0 with the banded regulariser of P and <P, Q>
 cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post,
-                        double* dot_out, bool fuse_update, hipStream_t s) {
+                        double* dot_out, bool fuse_update, hipStream_t s, void* xsol) {
     const int N = op->order;
     const int tc = prec_tc(prec), tv = prec_tvec(prec);
     const int* done = fuse_update ? &op->scal->done : nullptr;
@@ -132,7 +132,8 @@ cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post
     }
     hipError_t e = launch_tail(tv, tc, tc, Pin, op->T1, op->G[tc][a], op->G[tc][b], nblk,
                                (int)op->n[a], (int)op->n[b], (int)op->n[a], (int)op->n[b], pvec,
-                               &op->scal->beta, done, s, op->var_tail[tc]);
+                               &op->scal->beta, done, s, op->var_tail[tc],
+                               fuse_update ? xsol : nullptr, &op->scal->alpha);
     if (e != hipSuccess) return fail(CTA_ERR_HIP, "tail pass launch: %s", hipGetErrorString(e));
     void* cur = op->T1;
     void* nxt = op->T2;
@@ -487,14 +488,17 @@ cta_status cg_loop(cta_op_s* op, void* x, int prec, double rtol, int max_iter, i
     CTA_HIP(launch_fill_zero(op->vp, vb, s));
     CTA_HIP(launch_cg_setup(op->scal, rtol * rtol, max_iter, s));
     if (check_every < 1) check_every = 1;
+    // x += alpha p of each step is applied by the next step's tail pass (which
+    // reads p anyway); the last step's is flushed when the loop ends
     for (;;) {
         for (int c = 0; c < check_every; ++c) {
-            CTA_TRY(apply_normal(op, nullptr, op->vq, prec, POST_ALPHA, nullptr, true, s));
-            CTA_HIP(launch_cg_update(tv, x, op->vr, op->vp, op->vq, op->N, op->partials, op->scal, s));
+            CTA_TRY(apply_normal(op, nullptr, op->vq, prec, POST_ALPHA, nullptr, true, s, x));
+            CTA_HIP(launch_cg_update(tv, nullptr, op->vr, op->vp, op->vq, op->N, op->partials, op->scal, s));
         }
         CTA_TRY(read_scal(op, s));
         if (op->hscal->done != DONE_RUNNING) break;
     }
+    CTA_HIP(launch_x_flush(tv, x, op->vp, op->N, op->scal, s));
     *done_out = op->hscal->done;
     *iters_out = op->hscal->iters;
     return CTA_OK;
@@ -646,14 +650,16 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
                 int gdone = DONE_RUNNING;
                 for (;;) {
                     for (int c = 0; c < check; ++c) {
-                        CTA_TRY(apply_normal(op, nullptr, op->vq, CTA_PREC_BF16, POST_ALPHA, nullptr, true, s));
-                        CTA_HIP(launch_cg_update(DT_F32, op->vx, op->vr, op->vp, op->vq, n, op->partials,
+                        CTA_TRY(apply_normal(op, nullptr, op->vq, CTA_PREC_BF16, POST_ALPHA, nullptr, true, s,
+                                             op->vx));
+                        CTA_HIP(launch_cg_update(DT_F32, nullptr, op->vr, op->vp, op->vq, n, op->partials,
                                                  op->scal, s));
                     }
                     CTA_TRY(read_scal(op, s));
                     gdone = op->hscal->done;
                     if (gdone != DONE_RUNNING) break;
                 }
+                CTA_HIP(launch_x_flush(DT_F32, op->vx, op->vp, n, op->scal, s));
                 total += op->hscal->iters;
                 if (gdone == DONE_BREAKDOWN && op->hscal->iters == 0) {
                     done = DONE_BREAKDOWN;
@@ -739,10 +745,12 @@ extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void
     CTA_HIP(hipEventCreate(&e1));
     int best[3] = {0, 0, 0};
     float best_ms = 1e30f;
-    for (int combo = 0; combo < 8; ++combo) {
+    // tail and middle passes: 2 tile shapes each; last pass: 4 (two tile
+    // shapes, and two plane-grouped tile orders of the narrow one)
+    for (int combo = 0; combo < 16; ++combo) {
         op->var_tail[tc] = combo & 1;
         op->var_mid[tc] = (combo >> 1) & 1;
-        op->var_last[tc] = (combo >> 2) & 1;
+        op->var_last[tc] = (combo >> 2) & 3;
         void* out = combo == 0 ? op->vaux : op->vq;
         cta_status st = apply_normal(op, op->vp, out, chain, POST_NONE, nullptr, false, s);
         if (st != CTA_OK) return st;
@@ -768,7 +776,7 @@ extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void
             best_ms = med;
             best[0] = combo & 1;
             best[1] = (combo >> 1) & 1;
-            best[2] = (combo >> 2) & 1;
+            best[2] = (combo >> 2) & 3;
         }
     }
     (void)hipEventDestroy(e0);
@@ -791,7 +799,8 @@ extern "C" cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* hos
 extern "C" cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3) {
     if (!op || !host_variants3) return fail(CTA_ERR_ARG, "NULL argument");
     for (int i = 0; i < 3; ++i)
-        if (host_variants3[i] < 0 || host_variants3[i] > 1) return fail(CTA_ERR_ARG, "variant must be 0 or 1");
+        if (host_variants3[i] < 0 || host_variants3[i] > (i == 2 ? 3 : 1))
+            return fail(CTA_ERR_ARG, "variants must be 0 or 1 (tail, middle) and 0..3 (last)");
     const int tc = prec_tc(chain);
     op->var_tail[tc] = host_variants3[0];
     op->var_mid[tc] = host_variants3[1];

@@ -149,10 +149,12 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
         *out = total;
     } else if (post == POST_ALPHA) {
         scal->pq = total;
-        if (!(total > 0.0) || !__builtin_isfinite(total))
+        if (!(total > 0.0) || !__builtin_isfinite(total)) {
             scal->done = DONE_BREAKDOWN;
-        else
+            scal->alpha = 0.0;  // no step: the pending x update of the fused tail is void
+        } else {
             scal->alpha = scal->rho / total;
+        }
     } else if (post == POST_RHO) {
         const double rho = scal->rho;
         scal->beta = total / rho;
@@ -254,7 +256,7 @@ hipError_t launch_dot(int tv, const void* x, const void* y, int64_t n, double* p
 // C += alpha P; R -= alpha Q; partial of rho1 = <R, R>.  The finalize kernel
 // forms beta and the convergence test; P = R + beta P is fused into the first
 // pass of the next operator application.
-template <typename T>
+template <typename T, bool WITH_X>
 __global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
                                                       const T* __restrict__ p,
                                                       const T* __restrict__ q, int64_t n,
@@ -266,18 +268,20 @@ __global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __re
     double acc = 0.0;
     CTA_SWEEP(n,
               {
-                  v4 xv = *reinterpret_cast<v4*>(x + i);
+                  if constexpr (WITH_X) {
+                      v4 xv = *reinterpret_cast<v4*>(x + i);
+                      const v4 pv = *reinterpret_cast<const v4*>(p + i);
+                      xv = xv + alpha * pv;
+                      *reinterpret_cast<v4*>(x + i) = xv;
+                  }
                   v4 rv = *reinterpret_cast<v4*>(r + i);
-                  const v4 pv = *reinterpret_cast<const v4*>(p + i);
                   const v4 qv = *reinterpret_cast<const v4*>(q + i);
-                  xv = xv + alpha * pv;
                   rv = rv - alpha * qv;
-                  *reinterpret_cast<v4*>(x + i) = xv;
                   *reinterpret_cast<v4*>(r + i) = rv;
                   for (int u = 0; u < kItems; ++u) acc += (double)rv[u] * (double)rv[u];
               },
               {
-                  x[e] = x[e] + alpha * p[e];
+                  if constexpr (WITH_X) x[e] = x[e] + alpha * p[e];
                   const T rv = r[e] - alpha * q[e];
                   r[e] = rv;
                   acc += (double)rv * (double)rv;
@@ -285,17 +289,45 @@ __global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __re
     block_partial(acc, partials, red);
 }
 
+template <typename T>
+__global__ __launch_bounds__(CTA_WG) void k_x_flush(T* __restrict__ x, const T* __restrict__ p,
+                                                    int64_t n, const CgScalars* scal) {
+    const T alpha = (T)scal->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * CTA_WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * CTA_WG)
+        x[i] = x[i] + alpha * p[i];
+}
+
+hipError_t launch_x_flush(int tv, void* x, const void* p, int64_t n, const CgScalars* scal,
+                          hipStream_t s) {
+    ProfScope ps("x_flush", s);
+    const int g = plain_grid(n);
+    if (tv == DT_F64)
+        k_x_flush<double><<<g, CTA_WG, 0, s>>>((double*)x, (const double*)p, n, scal);
+    else if (tv == DT_F32)
+        k_x_flush<float><<<g, CTA_WG, 0, s>>>((float*)x, (const float*)p, n, scal);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_cg_update(int tv, void* x, void* r, const void* p, const void* q, int64_t n,
                             double* partials, CgScalars* scal, hipStream_t s) {
     const int g = red_grid(n);
     {
-        ProfScope ps(tv == DT_F64 ? "cg_update.f64" : "cg_update.f32", s);
-        if (tv == DT_F64)
-            k_cg_update<double><<<g, CTA_WG, 0, s>>>((double*)x, (double*)r, (const double*)p,
-                                                     (const double*)q, n, partials, scal);
+        ProfScope ps(x ? (tv == DT_F64 ? "cg_update.f64" : "cg_update.f32")
+                       : (tv == DT_F64 ? "cg_update_r.f64" : "cg_update_r.f32"), s);
+        if (tv == DT_F64 && x)
+            k_cg_update<double, true><<<g, CTA_WG, 0, s>>>((double*)x, (double*)r, (const double*)p,
+                                                           (const double*)q, n, partials, scal);
+        else if (tv == DT_F64)
+            k_cg_update<double, false><<<g, CTA_WG, 0, s>>>(nullptr, (double*)r, nullptr,
+                                                            (const double*)q, n, partials, scal);
+        else if (tv == DT_F32 && x)
+            k_cg_update<float, true><<<g, CTA_WG, 0, s>>>((float*)x, (float*)r, (const float*)p,
+                                                          (const float*)q, n, partials, scal);
         else if (tv == DT_F32)
-            k_cg_update<float><<<g, CTA_WG, 0, s>>>((float*)x, (float*)r, (const float*)p,
-                                                    (const float*)q, n, partials, scal);
+            k_cg_update<float, false><<<g, CTA_WG, 0, s>>>(nullptr, (float*)r, nullptr,
+                                                           (const float*)q, n, partials, scal);
         else
             return hipErrorInvalidValue;
         hipError_t e = hipGetLastError();

@@ -113,6 +113,7 @@ static hipError_t go_last(StridedArgs a, const StencilArgs<Tvec>& st, int* grid_
     constexpr int TN = 16 * CT * (CTA_WAVES / WJ);
     a.ntt = (a.trail + TN - 1) / TN;
     a.ntiles = a.lead * a.ntt;
+    if (a.pgroup > 0 && a.plane % TN != 0) a.pgroup = 0;
     const size_t xs = (size_t)TN * (a.kpad + 16 / sizeof(Tc)) * sizeof(Tc);
     const int nN = (int)st.ext[st.order - 1];
     const size_t win = normal_last_lds<Tvec, Tc, TN>(a.kpad, a.K, a.J, nN);
@@ -149,6 +150,21 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
     st.lam = d.lam;
     st.partials = partials;
     const int jt = (a.J + 15) / 16;
+    // variants 2 and 3: 32-column tiles walked plane-fastest (groups of 8
+    // planes, or all planes) along the second mode; fall back to variant 1
+    // when the shape does not allow it
+    a.pgroup = 0;
+    if (variant >= 2) {
+        const int64_t plane = d.order >= 3 ? d.stride[1] : 0;
+        const int nplane = d.order >= 3 ? (int)d.ext[1] : 0;
+        const int g = variant == 2 ? 8 : nplane;
+        if (plane > 0 && plane % 32 == 0 && g > 0 && nplane % g == 0 && plane * nplane == a.trail) {
+            a.plane = plane;
+            a.nplane = nplane;
+            a.pgroup = g;
+        }
+        variant = 1;
+    }
     if (variant == 1) {  // 32-column tiles: less LDS per workgroup, more workgroups per CU
         if (jt <= 2) return go_last<Tmid, Tvec, Tc, 1, 2, 1>(a, st, grid, done, s);
         if (jt <= 4) return go_last<Tmid, Tvec, Tc, 1, 4, 2>(a, st, grid, done, s);
@@ -250,7 +266,8 @@ static hipError_t tail_T(const TailArgs& a, size_t lds, hipStream_t s) {
 
 hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const Mat& M1,
                        const Mat& M2, int64_t nblk, int K1, int K2, int J1, int J2, void* Pvec,
-                       const double* beta, const int* done, hipStream_t s, int variant) {
+                       const double* beta, const int* done, hipStream_t s, int variant, void* Xsol,
+                       const double* alpha) {
     if (!tail_fits(tc, K1, J2) || J1 > 256) return hipErrorInvalidValue;
     const int ks = dt_kstep(tc);
     TailArgs a{};
@@ -259,6 +276,7 @@ hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const 
     a.k1pad = tail_k1pad(tc, K1);
     a.k2pad = (K2 + ks - 1) / ks * ks;
     a.nblk = nblk; a.Pvec = Pvec; a.beta = beta; a.done = done;
+    a.Xsol = Pvec ? Xsol : nullptr; a.alpha = alpha;
     a.nbg = tail_nb(tc, tout, K1, J1, J2);
     if (variant == 1 && tail_lds_nb(tc, tout, K1, J1, J2, 2 * a.nbg) <= 64 * 1024) a.nbg *= 2;
     if (a.k1pad > M1.ld || a.k2pad > M2.ld) return hipErrorInvalidValue;

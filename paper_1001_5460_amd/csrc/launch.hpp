@@ -72,9 +72,12 @@ hipError_t launch_strided(int tc, const void* X, void* Y, const Mat& M, int64_t 
 hipError_t launch_contig(int tc, const void* X, void* Y, const Mat& M, int64_t rows, int K, int J,
                          const int* done, hipStream_t s);
 bool tail_fits(int tc, int K1, int J2);
+// With Pvec: the chain input is p = X + beta p (X is r), written back to Pvec;
+// with Xsol as well: Xsol += alpha p (p before its update) on the same pass.
 hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const Mat& M1,
                        const Mat& M2, int64_t nblk, int K1, int K2, int J1, int J2, void* Pvec,
-                       const double* beta, const int* done, hipStream_t s, int variant = 0);
+                       const double* beta, const int* done, hipStream_t s, int variant = 0,
+                       void* Xsol = nullptr, const double* alpha = nullptr);
 // Last pass of the normal operator: Q = X x_1 M (mode 1 of a (K, trail)
 // tensor) + banded regulariser of P, with the FP64 <P, Q> reduced on device.
 hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q, const Mat& M,
@@ -94,9 +97,14 @@ hipError_t launch_residual(int tb, int tr, const void* B, const void* Q, void* r
 // out = <x, y> (FP64, deterministic two-stage reduction)
 hipError_t launch_dot(int tv, const void* x, const void* y, int64_t n, double* partials,
                       CgScalars* scal, double* out, hipStream_t s);
-// x += alpha p; r -= alpha q; rho1 = <r, r>; beta, convergence test (CG step)
+// x += alpha p (skipped when x is NULL: the tail pass applies it); r -= alpha q;
+// rho1 = <r, r>; beta, convergence test (CG step)
 hipError_t launch_cg_update(int tv, void* x, void* r, const void* p, const void* q, int64_t n,
                             double* partials, CgScalars* scal, hipStream_t s);
+// x += alpha p with the device alpha, whatever the done flag: applies the step
+// that the fused tail pass has not applied yet when an iteration loop ends
+hipError_t launch_x_flush(int tv, void* x, const void* p, int64_t n, const CgScalars* scal,
+                          hipStream_t s);
 // CG setup from device dots: threshold, rho, beta = 0, done flag
 hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s);
 // start of an iteration group after a reliable update (true <r, r> in scal->dot)

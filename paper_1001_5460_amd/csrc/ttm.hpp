@@ -45,7 +45,26 @@ struct StridedArgs {
     int64_t lead, trail;
     int64_t ntt;     // t tiles per b
     int64_t ntiles;  // lead * ntt
+    // Tile order of the normal-operator last pass (lead == 1).  pgroup == 0:
+    // tile i covers columns [i*TN, (i+1)*TN).  pgroup > 0: the trail is
+    // nplane planes of `plane` columns (plane % TN == 0, nplane % pgroup == 0);
+    // consecutive tiles walk the plane index fastest within groups of pgroup
+    // planes, so the neighbours that the regulariser reads along the plane
+    // mode are loaded by tiles that run at nearly the same time.
+    int64_t plane;
+    int nplane, pgroup;
 };
+
+// First column of tile `tile` of the last pass (see StridedArgs::pgroup).
+template <int TN>
+__device__ __forceinline__ int64_t last_tile_col(const StridedArgs& a, int64_t tile) {
+    if (a.pgroup <= 0) return tile * TN;
+    const int64_t cpp = a.plane / TN;            // tiles per plane
+    const int64_t per = cpp * a.pgroup;          // tiles per group of planes
+    const int64_t grp = tile / per, r = tile - grp * per;
+    const int64_t c = r / a.pgroup, ig = r - c * a.pgroup;
+    return (grp * a.pgroup + ig) * a.plane + c * TN;
+}
 
 struct TailArgs {
     int nbg;         // blocks per workgroup group
@@ -57,10 +76,14 @@ struct TailArgs {
     int K1, K2, J1, J2;
     int k1pad, k2pad;  // K1 rounded up to max(KSTEP, 16), K2 to KSTEP
     int64_t nblk;
-    // fused CG direction update p = r + beta p (the chain input is the new p)
+    // fused CG direction update p = r + beta p (the chain input is the new p);
+    // with Xsol, the previous step's x += alpha p (p before its update) is
+    // applied on the same pass, since p is read there anyway
     void* Pvec;
     const double* beta;
     const int* done;
+    void* Xsol;
+    const double* alpha;
 };
 
 struct ContigArgs {
@@ -249,7 +272,7 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
     const int ldx = a.kpad + 16 / (int)sizeof(Tc);
     const int K = a.K;
     const int trail = (int)a.trail;
-    const int t0 = (int)tile * TN;
+    const int t0 = (int)last_tile_col<TN>(a, tile);
     const int N = NORD > 0 ? NORD : st.order;
     const int nN = (int)st.ext[N - 1];
     const size_t xs_bytes = (size_t)TN * ldx * sizeof(Tc);
@@ -497,8 +520,11 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
     const int bout = a.J1 * a.J2;
     const Tc* __restrict__ M1 = reinterpret_cast<const Tc*>(a.M1);
     const Tc* __restrict__ M2 = reinterpret_cast<const Tc*>(a.M2);
-    Tin beta = cvt<Tin>(0.f);
-    if constexpr (FUSE_P) beta = cvt<Tin>(*a.beta);
+    Tin beta = cvt<Tin>(0.f), alpha = cvt<Tin>(0.f);
+    if constexpr (FUSE_P) {
+        beta = cvt<Tin>(*a.beta);
+        if (a.Xsol) alpha = cvt<Tin>(*a.alpha);
+    }
     const int nj2t = (a.J2 + 15) / 16;
     const int ni1t = a.k1pad / 16;
     const int nks2 = a.k2pad / T::KSTEP;
@@ -518,8 +544,10 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
             const int nv = (i1 < a.K1) ? max(0, min(VEC, a.K2 - k2)) : 0;
             typename T::frag xf = T::zfrag();
             if constexpr (FUSE_P) {
-                // p = r + beta * p on the fly; the new p is written back once
+                // x += alpha p (previous step, optional), then p = r + beta * p on
+                // the fly; the new p is written back once
                 Tin* __restrict__ Pv = reinterpret_cast<Tin*>(a.Pvec) + off0;
+                Tin* __restrict__ Xs = a.Xsol ? reinterpret_cast<Tin*>(a.Xsol) + off0 : nullptr;
                 const int64_t off = (int64_t)i1 * a.K2 + k2;
                 constexpr int LV = 16 / sizeof(Tin);
                 if (nv == VEC && aligned2 && (VEC % LV) == 0) {
@@ -528,6 +556,10 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
                     for (int h = 0; h < VEC / LV; ++h) {
                         const vin rv = *reinterpret_cast<const vin*>(X + off + h * LV);
                         const vin pv = *reinterpret_cast<const vin*>(Pv + off + h * LV);
+                        if (Xs) {
+                            const vin xv = *reinterpret_cast<const vin*>(Xs + off + h * LV);
+                            *reinterpret_cast<vin*>(Xs + off + h * LV) = xv + alpha * pv;
+                        }
                         const vin pn = rv + beta * pv;
                         *reinterpret_cast<vin*>(Pv + off + h * LV) = pn;
 #pragma unroll
@@ -537,7 +569,9 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
 #pragma unroll
                     for (int v = 0; v < VEC; ++v) {
                         if (v < nv) {
-                            const Tin pn = X[off + v] + beta * Pv[off + v];
+                            const Tin po = Pv[off + v];
+                            if (Xs) Xs[off + v] = Xs[off + v] + alpha * po;
+                            const Tin pn = X[off + v] + beta * po;
                             Pv[off + v] = pn;
                             xf[v] = cvt<Tc>(pn);
                         }

@@ -205,6 +205,89 @@ __global__ __launch_bounds__(CTA_WG) void k_conv_col(const bf16* __restrict__ in
     }
 }
 
+// Contiguous-mode form (stride 1, the last mode): each wave stages the rows
+// of its 16 voxels plus two on each side in LDS once (16-byte loads) and
+// reads the five tap fragments from there.  The tile loop is uniform over the
+// workgroup so that every wave reaches each barrier.  Same sums as k_conv.
+constexpr int LROWS = 16 + 4;
+constexpr int LPITCH = C + 8;  // bf16 per staged row (padding against bank conflicts)
+
+template <int EPI>
+__global__ __launch_bounds__(CTA_WG) void k_conv_line(const bf16* __restrict__ in,
+                                                      const bf16* __restrict__ Wr,
+                                                      const float* __restrict__ bias, const bf16* aux,
+                                                      bf16* out, int V, int nk) {
+    __shared__ __align__(16) bf16 rows[CTA_WAVES][LROWS * LPITCH];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, l16 = lane & 15;
+    bf16* rw = rows[wave];
+    bf16x8 wf[WID][2];
+#pragma unroll
+    for (int w = 0; w < WID; ++w)
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+            wf[w][rt] = *reinterpret_cast<const bf16x8*>(Wr + ((w * C) + rt * 16 + l16) * C + 8 * g);
+    float bv[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            bv[rt][r] = (EPI == EPI_RELU || EPI == EPI_RES) ? bias[rt * 16 + 4 * g + r] : 0.f;
+    const int ntiles = (V + 15) / 16;
+    for (int base = blockIdx.x * CTA_WAVES; base < ntiles; base += gridDim.x * CTA_WAVES) {
+        const int tile = base + wave;
+        const int v0 = tile * 16;
+        // stage voxels v0-2 .. v0+17 (row q holds voxel v0 - 2 + q; zero outside [0, V))
+        for (int u = lane; u < LROWS * 4; u += 64) {
+            const int q = u >> 2, part = u & 3;
+            const int v = v0 - 2 + q;
+            const bf16x8 val = (tile < ntiles && v >= 0 && v < V)
+                                   ? *reinterpret_cast<const bf16x8*>(in + (int64_t)v * C + 8 * part)
+                                   : zero8();
+            *reinterpret_cast<bf16x8*>(rw + q * LPITCH + 8 * part) = val;
+        }
+        __syncthreads();
+        const int vox = v0 + l16;
+        const bool inb = tile < ntiles && vox < V;
+        const int ik = inb ? vox % nk : 0;
+        floatx4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int w = 0; w < WID; ++w) {
+            const int d = w - WID / 2;
+            bf16x8 bfr = zero8();
+            if (inb && ik + d >= 0 && ik + d < nk)
+                bfr = *reinterpret_cast<const bf16x8*>(rw + (l16 + 2 + d) * LPITCH + 8 * g);
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[w][0], bfr, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[w][1], bfr, acc[1], 0, 0, 0);
+        }
+        __syncthreads();  // the rows are restaged by the next tile
+        if (!inb) continue;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const int ch = rt * 16 + 4 * g;
+            float y[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) y[r] = acc[rt][r] + bv[rt][r];
+            if constexpr (EPI != EPI_RELU) {
+                const bf16x4 a4 = *reinterpret_cast<const bf16x4*>(aux + (int64_t)vox * C + ch);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float av = (float)a4[r];
+                    if constexpr (EPI == EPI_MASK) y[r] = av > 0.f ? y[r] : 0.f;
+                    else y[r] += av;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) y[r] = fmaxf(y[r], 0.f);
+            }
+            bf16x4 o;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] = (bf16)y[r];
+            *reinterpret_cast<bf16x4*>(out + (int64_t)vox * C + ch) = o;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ weight gradient
 constexpr int WCH = 64;        // voxels per chunk
 constexpr int WLD = WCH + 8;   // LDS row pitch (bf16)
@@ -593,11 +676,12 @@ extern "C" cta_status cta_ws_destroy(cta_ws w) {
 
 extern "C" int64_t cta_ws_num_params(cta_ws w) { return w ? w->P : 0; }
 
-// tracer names per epilogue: [EPI][flat, column]
-static const char* const kConvName[4][2] = {{"ws_conv.flat.relu", "ws_conv.col.relu"},
-                                            {"ws_conv.flat.res", "ws_conv.col.res"},
-                                            {"ws_conv.flat.mask", "ws_conv.col.mask"},
-                                            {"ws_conv.flat.add", "ws_conv.col.add"}};
+// tracer names per epilogue: [EPI][flat, column, line]
+static const char* const kConvName[4][3] = {
+    {"ws_conv.flat.relu", "ws_conv.col.relu", "ws_conv.line.relu"},
+    {"ws_conv.flat.res", "ws_conv.col.res", "ws_conv.line.res"},
+    {"ws_conv.flat.mask", "ws_conv.col.mask", "ws_conv.line.mask"},
+    {"ws_conv.flat.add", "ws_conv.col.add", "ws_conv.line.add"}};
 
 template <int EPI>
 static void conv_go(cta_ws_s* w, const bf16* in, const bf16* Wr, const float* bias, const bf16* aux,
@@ -608,6 +692,9 @@ static void conv_go(cta_ws_s* w, const bf16* in, const bf16* Wr, const float* bi
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((ncols + CTA_WAVES - 1) / CTA_WAVES, 65536));
         ProfScope ps(kConvName[EPI][1], s);
         k_conv_col<EPI><<<grid, CTA_WG, 0, s>>>(in, Wr, bias, aux, out, nk, sk, tb, ncols);
+    } else if (sk == 1) {
+        ProfScope ps(kConvName[EPI][2], s);
+        k_conv_line<EPI><<<w->conv_grid, CTA_WG, 0, s>>>(in, Wr, bias, aux, out, w->V, nk);
     } else {
         ProfScope ps(kConvName[EPI][0], s);
         k_conv<EPI><<<w->conv_grid, CTA_WG, 0, s>>>(in, Wr, bias, aux, out, w->V, nk, sk);

@@ -115,8 +115,8 @@ def test_tile_variants_match_oracle(n, m, chain):
     P = dev(np.random.default_rng(11).standard_normal(n), dt)
     ref = ref_op(host(P))
     outs = []
-    for combo in range(8):
-        cta.cta_op_set_tuning(op.handle, chain, combo & 1, (combo >> 1) & 1, (combo >> 2) & 1)
+    for combo in range(16):
+        cta.cta_op_set_tuning(op.handle, chain, combo & 1, (combo >> 1) & 1, (combo >> 2) & 3)
         Q = op.apply(P, chain=chain)
         torch.cuda.synchronize()
         assert rel_fro(host(Q), ref) <= TOL[chain]
