@@ -141,6 +141,11 @@ __device__ void last_tiles(const BatchProblem& pb, unsigned char* smem, int memb
     st.order = 3;
     st.lam = pb.lam;
     st.partials = nullptr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        fastdiv_init((uint32_t)st.stride[k], &st.smul[k], &st.sshift[k]);
+        fastdiv_init((uint32_t)st.ext[k], &st.emul[k], &st.eshift[k]);
+    }
     for (int64_t tile = member; tile < a.ntiles; tile += S)
         normal_last_tile<float, float, float, JT, WJ, CT, 3>(a, tile, smem, st, dot);
 }

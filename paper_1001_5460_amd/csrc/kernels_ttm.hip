@@ -149,6 +149,12 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
     st.order = d.order;
     st.lam = d.lam;
     st.partials = partials;
+    for (int k = 0; k < 8; ++k) {
+        fastdiv_init((uint32_t)std::max<int64_t>(1, std::min<int64_t>(d.stride[k], INT32_MAX)), &st.smul[k],
+                     &st.sshift[k]);
+        fastdiv_init((uint32_t)std::max<int64_t>(1, std::min<int64_t>(d.ext[k], INT32_MAX)), &st.emul[k],
+                     &st.eshift[k]);
+    }
     const int jt = (a.J + 15) / 16;
     // variants 2 and 3: 32-column tiles walked plane-fastest (groups of 8
     // planes, or all planes) along the second mode; fall back to variant 1

@@ -39,6 +39,17 @@ struct CgScalars {
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_BREAKDOWN = 2, DONE_MAXITER = 3 };
 
+// Multiply-high division by a constant (Granlund and Montgomery, "Division by
+// invariant integers using multiplication", 1994): with l = ceil(log2 d) and
+// mul = floor(2^32 (2^l - d) / d) + 1, floor(n / d) = (mulhi(mul, n) + n) >> l
+// for every n < 2^31 (the sum cannot overflow 32 bits).
+__host__ __device__ inline void fastdiv_init(uint32_t d, uint32_t* mul, int* shift) {
+    int l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    *shift = l;
+    *mul = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+}
+
 // Banded regulariser of the normal operator (half-bandwidth <= 2).
 struct StencilDesc {
     const void* P;

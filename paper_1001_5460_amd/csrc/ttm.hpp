@@ -34,7 +34,16 @@ struct StencilArgs {
     int order;
     double lam;
     double* partials;       // one double per workgroup
+    // division by stride[k] and ext[k] as multiply-high and shift (see
+    // fastdiv_init); valid for dividends below 2^31
+    uint32_t smul[8], emul[8];
+    int sshift[8], eshift[8];
 };
+
+// floor(n / d) for n < 2^31 from (mul, shift) = fastdiv_init(d)
+__device__ __forceinline__ int fast_div(int n, uint32_t mul, int shift) {
+    return (int)((__umulhi(mul, (uint32_t)n) + (uint32_t)n) >> shift);
+}
 
 struct StridedArgs {
     const void* X;
@@ -433,7 +442,7 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
                     w[E + e] = pc[e];
                     w[2 * E + e] = pr[e];
                 }
-                const int i0 = t % nN;
+                const int i0 = t - fast_div(t, st.emul[N - 1], st.eshift[N - 1]) * nN;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const Tv* bN = bandN + (i0 + e) * 5;
@@ -441,18 +450,20 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
                     for (int d = -2; d <= 2; ++d) reg[e] += bN[d + 2] * w[E + e + d];
                 }
             }
+            const Tv* __restrict__ pb = P + base;
             for (int k = 1; k < N - 1; ++k) {
                 const Tv* __restrict__ rb = st.rband[k];
                 if (!rb) continue;
                 const int sk = (int)st.stride[k], nk = (int)st.ext[k];
-                const int ik = (t / sk) % nk;
+                const int u = fast_div(t, st.smul[k], st.sshift[k]);
+                const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
                 const Tv* br = rb + ik * 5;
                 vt nbv[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
                     const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
-                    nbv[q] = *reinterpret_cast<const vt*>(P + base + (int64_t)dd * sk);
+                    nbv[q] = *reinterpret_cast<const vt*>(pb + dd * sk);
                 }
                 reg += br[2] * pc;
 #pragma unroll
