@@ -21,6 +21,8 @@ no blocking, fusion or reordering beyond what the cited definition states:
 * ``judge``   -- the FP64 relative residual used to judge any solution.
 * ``wsnet``   -- the learned warm-start network (separable per-mode
   convolutions, Table 1) with forward, backward (App. A.8) and Adam.
+* ``precond`` -- the tensor-inverse preconditioner (the separable part of the
+  operator inverted mode by mode, Sec. 3) and preconditioned CG.
 """
 from .tensor import mode_product, multi_mode_product, inner
 from .normal import (
@@ -37,6 +39,7 @@ from .cg import cg, CGResult, lanczos_extremes
 from .dense import assemble, dense_solve
 from .judge import relative_residual
 from . import wsnet
+from . import precond
 
 __all__ = [
     "mode_product", "multi_mode_product", "inner",
