@@ -168,6 +168,21 @@ cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
 cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3);
 cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3);
 
+/* Tensor-inverse preconditioner (Sec. 3: a separable operator is inverted
+ * mode by mode).  The separable part of N with each G_k replaced by
+ * G_k + c R_k is inverted per mode:
+ *     M^-1(R) = R x_1 (G_1 + c R_1)^-1 ... x_N (G_N + c R_N)^-1,
+ * exact for lambda = 0 and c = 0.  The inverses are formed on the host in
+ * FP64 (Cholesky; CTA_ERR_ARG if some G_k + c R_k is not positive definite)
+ * and kept on the device in F64, F32 and BF16; a later call replaces them,
+ * c < 0 removes the preconditioner.  Synchronous. */
+cta_status cta_op_set_preconditioner(cta_op op, double c);
+/* Z = M^-1(R) in `chain` precision (F64 tensors for CTA_PREC_F64, F32
+ * otherwise); optional FP64 <R, Z> written to the device double *dot.
+ * Asynchronous. */
+cta_status cta_apply_precond(cta_op op, const void* R, void* Z, cta_dtype dtype, cta_precision chain,
+                             double* dot, void* stream);
+
 /* ------------------------------------------------------------------------
  * Conjugate-gradient solve (Fig. Tensor_CG) of N(X) = B.
  *
@@ -200,6 +215,11 @@ typedef struct {
     double inner_rtol;  /* refinement: inner relative tolerance (e.g. 1e-2) */
     int max_refine;     /* refinement: outer steps */
     int check_every;    /* host reads the convergence flag every this many iterations */
+    int precond;        /* 1: preconditioned CG with the operator's tensor-inverse
+                           preconditioner (cta_op_set_preconditioner); the
+                           iteration uses z = M^-1 r for the search direction and
+                           <r, z> for the step lengths, the stopping test stays
+                           ||r|| <= rtol ||B|| (not for cta_solve_batched) */
 } cta_cg_opts;
 
 typedef struct {
@@ -212,7 +232,7 @@ typedef struct {
 } cta_cg_info;
 
 /* Defaults: F32, rtol 1e-6, max_iter 10000, no start, inner_rtol 1e-2,
- * max_refine 30, check_every 16. */
+ * max_refine 30, check_every 16, no preconditioner. */
 void cta_cg_opts_default(cta_cg_opts* opts);
 
 cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype dtype,

@@ -41,7 +41,8 @@ class _CgOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("x0_given", ctypes.c_int),
                 ("fallback_zero", ctypes.c_int), ("inner_rtol", ctypes.c_double),
-                ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class _CgInfo(ctypes.Structure):
@@ -68,6 +69,8 @@ _SIGS = {
     "cta_forward": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int, _P]),
     "cta_rhs": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int, _P]),
     "cta_apply_normal_op": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "cta_op_set_preconditioner": (ctypes.c_int, [_P, ctypes.c_double]),
+    "cta_apply_precond": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "cta_cg_opts_default": (None, [ctypes.POINTER(_CgOpts)]),
     "cta_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(_CgOpts),
                                     ctypes.POINTER(_CgInfo), _P]),
@@ -289,6 +292,18 @@ def cta_apply_normal_op(h, P, Q, chain="f32", dot=None, stream=None):
     return Q
 
 
+def cta_op_set_preconditioner(h, c):
+    """Tensor-inverse preconditioner (G_k + c R_k)^-1 per mode; c < 0 removes it."""
+    _check(load_library().cta_op_set_preconditioner(h, float(c)))
+
+
+def cta_apply_precond(h, R, Z, chain="f32", dot=None, stream=None):
+    dp = _dev(dot, "dot") if dot is not None else None
+    _check(load_library().cta_apply_precond(h, _dev(R, "R"), _dev(Z, "Z"), _dt(R), _PREC[chain], dp,
+                                            _stream(stream)))
+    return Z
+
+
 def cta_tune_op(h, chain="bf16", reps=5, stream=None):
     """Pick the fastest bit-identical tile shapes of the operator's passes; returns them."""
     lib = load_library()
@@ -479,6 +494,15 @@ class Operator:
 
     def tune(self, chain="bf16", reps=5, stream=None):
         return cta_tune_op(self.handle, chain, reps, stream)
+
+    def set_preconditioner(self, c):
+        cta_op_set_preconditioner(self.handle, c)
+
+    def precond(self, R, Z=None, chain="f32", dot=None, stream=None):
+        torch = _torch()
+        if Z is None:
+            Z = torch.empty_like(R)
+        return cta_apply_precond(self.handle, R, Z, chain, dot, stream)
 
     def solve(self, B, X=None, stream=None, **opts):
         torch = _torch()

@@ -42,6 +42,12 @@ struct cta_op_s {
     int var_tail[3] = {0, 0, 0};
     int var_mid[3] = {0, 0, 0};
     int var_last[3] = {0, 0, 0};
+    // host FP64 copies of G_k and R_k (R_k empty: no regulariser on mode k)
+    std::vector<double> hG[CTA_MAX_ORDER], hR[CTA_MAX_ORDER];
+    // tensor-inverse preconditioner: (G_k + c R_k)^-1 per compute dtype
+    cta::Mat Pinv[3][CTA_MAX_ORDER];
+    bool has_pc = false;
+    double pc_c = 0.0;
 };
 
 namespace cta {
@@ -50,5 +56,11 @@ cta_status fail(cta_status st, const char* fmt, ...);
 // and with xsol the previous CG step's xsol += alpha p is applied on the
 // same pass.
 cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post, double* dot_out,
-                        bool fuse_update, hipStream_t s, void* xsol = nullptr);
+                        bool fuse_update, hipStream_t s, void* xsol = nullptr,
+                        const void* fuse_src = nullptr);
+// Z = M^-1(R) (the tensor-inverse preconditioner) with <R, Z> reduced on the
+// device and handled by `post`; gated: every kernel exits when the solve's
+// done flag is set.
+cta_status apply_precond(cta_op_s* op, const void* R, void* Z, int prec, int post, double* dot_out,
+                         bool gated, hipStream_t s);
 }  // namespace cta

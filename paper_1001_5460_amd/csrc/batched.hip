@@ -508,6 +508,7 @@ static cta_status check_batch(int count, const cta_op* ops, const void* const* B
     if (dtype != CTA_F32 || opts->precision != CTA_PREC_F32)
         return fail(CTA_ERR_DTYPE, "the batched solver runs in CTA_PREC_F32 on CTA_F32 tensors");
     if (opts->x0_given) return fail(CTA_ERR_UNSUPPORTED, "the batched solver starts from zero");
+    if (opts->precond) return fail(CTA_ERR_UNSUPPORTED, "the batched solver has no preconditioner");
     for (int i = 0; i < count; ++i) {
         if (!ops[i] || !B[i] || !X[i]) return fail(CTA_ERR_ARG, "problem %d: NULL handle or tensor", i);
         if (ops[i]->user_order != 3) return fail(CTA_ERR_SHAPE, "problem %d: the batched solver takes order-3 problems", i);

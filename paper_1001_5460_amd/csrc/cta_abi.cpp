@@ -113,7 +113,8 @@ static int prec_tvec(int prec) { return prec == CTA_PREC_F64 ? DT_F64 : DT_F32; 
 //   middle: strided passes on modes N-3 .. 1
 //   last  : mode 0 with the banded regulariser of P and <P, Q>
 cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post,
-                        double* dot_out, bool fuse_update, hipStream_t s, void* xsol) {
+                        double* dot_out, bool fuse_update, hipStream_t s, void* xsol,
+                        const void* fuse_src) {
     const int N = op->order;
     const int tc = prec_tc(prec), tv = prec_tvec(prec);
     const int* done = fuse_update ? &op->scal->done : nullptr;
@@ -126,7 +127,7 @@ cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post
     const void* Pin = P;
     void* pvec = nullptr;
     if (fuse_update) {
-        Pin = op->vr;   // chain input is r + beta p, written to p
+        Pin = fuse_src ? fuse_src : op->vr;   // chain input is r (or z) + beta p, written to p
         pvec = op->vp;
         P = op->vp;
     }
@@ -161,6 +162,50 @@ cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post
                            op->N / op->n[0], st, op->partials, op->scal, post, dot_out, done, s,
                            op->var_last[tc]);
     if (e != hipSuccess) return fail(CTA_ERR_HIP, "last pass launch: %s", hipGetErrorString(e));
+    return CTA_OK;
+}
+
+// Z = M^-1(R): mode products of R with (G_k + c R_k)^-1, the same passes as
+// the normal operator (fused tail, strided middle modes, last pass) with no
+// regulariser in the last pass, whose FP64 dot gives <R, Z>.
+cta_status apply_precond(cta_op_s* op, const void* R, void* Z, int prec, int post, double* dot_out,
+                         bool gated, hipStream_t s) {
+    if (!op->has_pc) return fail(CTA_ERR_ARG, "no preconditioner: call cta_op_set_preconditioner first");
+    const int N = op->order;
+    const int tc = prec_tc(prec), tv = prec_tvec(prec);
+    const int* done = gated ? &op->scal->done : nullptr;
+    const int a = N - 2, b = N - 1;
+    const int64_t nblk = op->N / (op->n[a] * op->n[b]);
+    hipError_t e = launch_tail(tv, tc, tc, R, op->T1, op->Pinv[tc][a], op->Pinv[tc][b], nblk,
+                               (int)op->n[a], (int)op->n[b], (int)op->n[a], (int)op->n[b], nullptr,
+                               nullptr, done, s, op->var_tail[tc]);
+    if (e != hipSuccess) return fail(CTA_ERR_HIP, "preconditioner tail launch: %s", hipGetErrorString(e));
+    void* cur = op->T1;
+    void* nxt = op->T2;
+    for (int k = N - 3; k >= 1; --k) {
+        int64_t lead = 1, trail = 1;
+        for (int l = 0; l < k; ++l) lead *= op->n[l];
+        for (int l = k + 1; l < N; ++l) trail *= op->n[l];
+        e = launch_strided(tc, cur, nxt, op->Pinv[tc][k], lead, (int)op->n[k], (int)op->n[k], trail, done, s,
+                           op->var_mid[tc]);
+        if (e != hipSuccess) return fail(CTA_ERR_HIP, "preconditioner mode pass: %s", hipGetErrorString(e));
+        std::swap(cur, nxt);
+    }
+    StencilDesc st{};
+    st.P = R;
+    st.order = N;
+    st.lam = 0.0;
+    int64_t stride = 1;
+    for (int k = N - 1; k >= 0; --k) {
+        st.ext[k] = op->n[k];
+        st.stride[k] = stride;
+        stride *= op->n[k];
+        st.rband[k] = nullptr;
+    }
+    e = launch_normal_last(tc, tv, tc, cur, Z, op->Pinv[tc][0], (int)op->n[0], (int)op->n[0],
+                           op->N / op->n[0], st, op->partials, op->scal, post, dot_out, done, s,
+                           op->var_last[tc]);
+    if (e != hipSuccess) return fail(CTA_ERR_HIP, "preconditioner last pass: %s", hipGetErrorString(e));
     return CTA_OK;
 }
 
@@ -327,6 +372,10 @@ extern "C" cta_status cta_op_create(cta_op* out, int order, const int64_t* n, co
         big *= std::max(op->n[k], op->m[k]);
     }
     op->big = big;
+    for (int k = 0; k < op->order; ++k) {
+        op->hG[k] = G[k];
+        op->hR[k] = R[k];
+    }
     cta_status st = CTA_OK;
     auto& al = op->allocs;
     size_t& acc = op->dev_bytes;
@@ -454,6 +503,7 @@ extern "C" void cta_cg_opts_default(cta_cg_opts* o) {
     o->max_iter = 10000;
     o->x0_given = 0;
     o->fallback_zero = 0;
+    o->precond = 0;
     o->inner_rtol = 1e-2;
     o->max_refine = 30;
     o->check_every = 16;
@@ -482,18 +532,22 @@ static cta_status read_scal(cta_op_s* op, hipStream_t s) {
 // Inner CG loop on the handle's vectors: x (vx or the user's X), r = vr, p = vp,
 // q = vq, with scal->rho and scal->bnorm2 already set.  Returns the final done flag.
 cta_status cg_loop(cta_op_s* op, void* x, int prec, double rtol, int max_iter, int check_every,
-                   hipStream_t s, int* done_out, int* iters_out) {
+                   hipStream_t s, int* done_out, int* iters_out, bool pc) {
     const int tv = prec_tvec(prec);
     const size_t vb = (size_t)op->N * dt_size(tv);
     CTA_HIP(launch_fill_zero(op->vp, vb, s));
-    CTA_HIP(launch_cg_setup(op->scal, rtol * rtol, max_iter, s));
+    // preconditioned: z = M^-1 r in vaux and <r, z> before the first step
+    if (pc) CTA_TRY(apply_precond(op, op->vr, op->vaux, prec, POST_DOT, &op->scal->rz, false, s));
+    CTA_HIP(launch_cg_setup(op->scal, rtol * rtol, max_iter, s, pc ? 1 : 0));
     if (check_every < 1) check_every = 1;
     // x += alpha p of each step is applied by the next step's tail pass (which
     // reads p anyway); the last step's is flushed when the loop ends
     for (;;) {
         for (int c = 0; c < check_every; ++c) {
-            CTA_TRY(apply_normal(op, nullptr, op->vq, prec, POST_ALPHA, nullptr, true, s, x));
+            CTA_TRY(apply_normal(op, nullptr, op->vq, prec, POST_ALPHA, nullptr, true, s, x,
+                                 pc ? op->vaux : nullptr));
             CTA_HIP(launch_cg_update(tv, nullptr, op->vr, op->vp, op->vq, op->N, op->partials, op->scal, s));
+            if (pc) CTA_TRY(apply_precond(op, op->vr, op->vaux, prec, POST_RZ, nullptr, true, s));
         }
         CTA_TRY(read_scal(op, s));
         if (op->hscal->done != DONE_RUNNING) break;
@@ -541,6 +595,8 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
     const int prec = opts->precision;
     if (prec < CTA_PREC_F64 || prec > CTA_PREC_BF16_RELIABLE) return fail(CTA_ERR_ARG, "bad precision");
     const bool mixed = prec == CTA_PREC_BF16_REFINE || prec == CTA_PREC_BF16_RELIABLE;
+    const bool pc = opts->precond != 0;
+    if (pc && !op->has_pc) return fail(CTA_ERR_ARG, "precond = 1 but no preconditioner was set");
     if (!(opts->rtol >= 0) || opts->max_iter < 0) return fail(CTA_ERR_ARG, "bad rtol or max_iter");
     const int want = (prec == CTA_PREC_F64 || mixed) ? DT_F64 : DT_F32;
     if ((int)dtype != want)
@@ -573,7 +629,7 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
             CTA_HIP(launch_cast(tv, tv, B, op->vr, n, s));
             CTA_HIP(launch_dot(tv, B, B, n, op->partials, op->scal, &op->scal->rho, s));
         }
-        CTA_TRY(cg_loop(op, X, prec, opts->rtol, opts->max_iter, check, s, &done, &iters));
+        CTA_TRY(cg_loop(op, X, prec, opts->rtol, opts->max_iter, check, s, &done, &iters, pc));
         int total = iters;
         double rel_rec = std::sqrt(std::max(0.0, op->hscal->rho) / std::max(op->hscal->bnorm2, 1e-300));
         double bn2 = op->hscal->bnorm2;
@@ -586,7 +642,7 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
             CTA_TRY(apply_normal(op, X, op->vq, prec, POST_NONE, nullptr, false, s));
             CTA_HIP(launch_residual(tv, tv, B, op->vq, op->vr, n, op->partials, op->scal, &op->scal->rho, s));
             CTA_HIP(launch_dot(tv, B, B, n, op->partials, op->scal, &op->scal->bnorm2, s));
-            CTA_TRY(cg_loop(op, X, prec, opts->rtol, opts->max_iter - total, check, s, &done, &iters));
+            CTA_TRY(cg_loop(op, X, prec, opts->rtol, opts->max_iter - total, check, s, &done, &iters, pc));
             total += iters;
             rel_rec = std::sqrt(std::max(0.0, op->hscal->rho) / std::max(op->hscal->bnorm2, 1e-300));
             CTA_TRY(true_residual(op, B, X, tv, s, &rel_true));
@@ -646,14 +702,18 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
                 // iterate until the recursive residual has dropped by eta since this
                 // update (or a little below the target, which the true residual then checks)
                 const double thr = std::max(eta * eta * rr, 0.25 * target);
-                CTA_HIP(launch_cg_group(op->scal, thr, opts->max_iter, steps > 0 ? 1 : 0, s));
+                if (pc)
+                    CTA_TRY(apply_precond(op, op->vr, op->vaux, CTA_PREC_BF16, POST_DOT, &op->scal->dot2, false, s));
+                CTA_HIP(launch_cg_group(op->scal, thr, opts->max_iter, steps > 0 ? 1 : 0, s, pc ? 1 : 0));
                 int gdone = DONE_RUNNING;
                 for (;;) {
                     for (int c = 0; c < check; ++c) {
                         CTA_TRY(apply_normal(op, nullptr, op->vq, CTA_PREC_BF16, POST_ALPHA, nullptr, true, s,
-                                             op->vx));
+                                             op->vx, pc ? op->vaux : nullptr));
                         CTA_HIP(launch_cg_update(DT_F32, nullptr, op->vr, op->vp, op->vq, n, op->partials,
                                                  op->scal, s));
+                        if (pc)
+                            CTA_TRY(apply_precond(op, op->vr, op->vaux, CTA_PREC_BF16, POST_RZ, nullptr, true, s));
                     }
                     CTA_TRY(read_scal(op, s));
                     gdone = op->hscal->done;
@@ -697,7 +757,7 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
             CTA_HIP(launch_fill_zero(op->vx, (size_t)n * 4, s));
             CTA_HIP(launch_dot(DT_F32, op->vr, op->vr, n, op->partials, op->scal, &op->scal->bnorm2, s));
             int idone = 0, iit = 0;
-            CTA_TRY(cg_loop(op, op->vx, CTA_PREC_BF16, eta, opts->max_iter, check, s, &idone, &iit));
+            CTA_TRY(cg_loop(op, op->vx, CTA_PREC_BF16, eta, opts->max_iter, check, s, &idone, &iit, pc));
             total += iit;
             if (idone == DONE_BREAKDOWN && iit == 0) {
                 done = DONE_BREAKDOWN;
@@ -806,4 +866,89 @@ extern "C" cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const in
     op->var_mid[tc] = host_variants3[1];
     op->var_last[tc] = host_variants3[2];
     return CTA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tensor-inverse preconditioner: (G_k + c R_k)^-1 per mode, by Cholesky
+// factorisation and forward / back substitution of the unit vectors (FP64).
+namespace {
+bool spd_inverse(const std::vector<double>& A, int n, std::vector<double>& inv) {
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double d = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(d > 0.0)) return false;
+        const double ljj = std::sqrt(d);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = v / ljj;
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    std::vector<double> y(n);
+    for (int c = 0; c < n; ++c) {
+        for (int i = 0; i < n; ++i) {  // L y = e_c
+            double v = i == c ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * y[k];
+            y[i] = v / L[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {  // L^T x = y
+            double v = y[i];
+            for (int k = i + 1; k < n; ++k) v -= L[(size_t)k * n + i] * inv[(size_t)k * n + c];
+            inv[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+        }
+    }
+    return true;
+}
+
+void release_mat(cta_op_s* op, Mat& m) {
+    if (!m.p) return;
+    void* p = const_cast<void*>(m.p);
+    auto it = std::find(op->allocs.begin(), op->allocs.end(), p);
+    if (it != op->allocs.end()) op->allocs.erase(it);
+    (void)hipFree(p);
+    m = Mat{};
+}
+}  // namespace
+
+extern "C" cta_status cta_op_set_preconditioner(cta_op op, double c) {
+    if (!op) return fail(CTA_ERR_ARG, "op is NULL");
+    if (!std::isfinite(c)) return fail(CTA_ERR_ARG, "c must be finite");
+    if (hipDeviceSynchronize() != hipSuccess) return fail(CTA_ERR_HIP, "synchronize failed");
+    for (int dt = 0; dt < 3; ++dt)
+        for (int k = 0; k < op->order; ++k) release_mat(op, op->Pinv[dt][k]);
+    op->has_pc = false;
+    if (c < 0) return CTA_OK;
+    size_t acc = 0;
+    for (int k = 0; k < op->order; ++k) {
+        const int nk = (int)op->n[k];
+        std::vector<double> M = op->hG[k], inv;
+        if (!op->hR[k].empty())
+            for (size_t i = 0; i < M.size(); ++i) M[i] += c * op->hR[k][i];
+        if (!spd_inverse(M, nk, inv))
+            return fail(CTA_ERR_ARG, "G_%d + c R_%d is not positive definite", k - op->lift, k - op->lift);
+        for (int dt = 0; dt < 3; ++dt) {
+            cta_status st = upload_mat(inv.data(), nk, nk, false, dt, &op->Pinv[dt][k], op->allocs, acc);
+            if (st != CTA_OK) return st;
+        }
+    }
+    op->dev_bytes += acc;
+    op->has_pc = true;
+    op->pc_c = c;
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_apply_precond(cta_op op, const void* R, void* Z, cta_dtype dtype,
+                                        cta_precision chain, double* dot, void* stream) {
+    if (!op || !R || !Z) return fail(CTA_ERR_ARG, "NULL argument");
+    if (chain != CTA_PREC_F64 && chain != CTA_PREC_F32 && chain != CTA_PREC_BF16)
+        return fail(CTA_ERR_ARG, "chain precision must be F64, F32 or BF16");
+    const int want = chain == CTA_PREC_F64 ? CTA_F64 : CTA_F32;
+    if ((int)dtype != want) return fail(CTA_ERR_DTYPE, "R and Z must be %s", want == CTA_F64 ? "CTA_F64" : "CTA_F32");
+    if (R == Z) return fail(CTA_ERR_ARG, "R and Z must not overlap");
+    if (!tail_fits(prec_tc(chain), (int)op->n[op->order - 2], (int)op->n[op->order - 1]))
+        return fail(CTA_ERR_UNSUPPORTED, "operator chain not supported in this precision");
+    return apply_precond(op, R, Z, chain, dot ? POST_DOT : POST_NONE, dot, false, (hipStream_t)stream);
 }

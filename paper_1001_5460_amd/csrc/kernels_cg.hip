@@ -125,7 +125,7 @@ hipError_t launch_axpby(int tv, double a, const void* x, double b, void* y, int6
 // One workgroup: total = sum of partials in index order, then the scalar step.
 __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ partials, int n,
                                                    CgScalars* scal, int post, double* out) {
-    if ((post == POST_ALPHA || post == POST_RHO) && scal->done) return;
+    if ((post == POST_ALPHA || post == POST_RHO || post == POST_RZ) && scal->done) return;
     __shared__ double red[16];
     // thread i sums partials i, i+1024, i+2048, ... (loads issued four at a time)
     double acc = 0.0;
@@ -153,11 +153,11 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
             scal->done = DONE_BREAKDOWN;
             scal->alpha = 0.0;  // no step: the pending x update of the fused tail is void
         } else {
-            scal->alpha = scal->rho / total;
+            scal->alpha = (scal->precond ? scal->rz : scal->rho) / total;
         }
     } else if (post == POST_RHO) {
         const double rho = scal->rho;
-        scal->beta = total / rho;
+        if (!scal->precond) scal->beta = total / rho;
         scal->rho = total;
         scal->iters += 1;
         if (!__builtin_isfinite(total))
@@ -166,6 +166,13 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
             scal->done = DONE_CONVERGED;
         else if (scal->iters >= scal->max_iter)
             scal->done = DONE_MAXITER;
+    } else if (post == POST_RZ) {
+        if (!(total > 0.0) || !__builtin_isfinite(total)) {
+            scal->done = DONE_BREAKDOWN;  // the preconditioner is not positive definite
+        } else {
+            scal->beta = total / scal->rz;
+            scal->rz = total;
+        }
     }
 }
 
@@ -336,8 +343,9 @@ hipError_t launch_cg_update(int tv, void* x, void* r, const void* p, const void*
     return launch_finalize(partials, g, scal, POST_RHO, nullptr, s);
 }
 
-__global__ void k_cg_setup(CgScalars* scal, double rtol2, int max_iter) {
+__global__ void k_cg_setup(CgScalars* scal, double rtol2, int max_iter, int precond) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    scal->precond = precond;
     scal->threshold = rtol2 * scal->bnorm2;
     scal->rho0 = scal->rho;
     scal->beta = 0.0;
@@ -360,11 +368,20 @@ __global__ void k_cg_setup(CgScalars* scal, double rtol2, int max_iter) {
 // residual's <r, r> is in scal->dot; the search direction is kept and
 // beta = rho_true / rho_k, where rho_k = rho / beta is the residual norm
 // before the last CG step.
-__global__ void k_cg_group(CgScalars* scal, double threshold, int max_iter, int keep_dir) {
+__global__ void k_cg_group(CgScalars* scal, double threshold, int max_iter, int keep_dir,
+                           int precond) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double rt = keep_dir ? scal->dot : scal->rho;
     double beta = 0.0;
-    if (keep_dir && scal->rho > 0.0) beta = scal->beta * rt / scal->rho;
+    scal->precond = precond;
+    if (precond) {
+        // the same rescaling with <r, z>: beta = <r, z>_true / <r, z>_k
+        const double zt = scal->dot2;
+        if (keep_dir && scal->rz > 0.0) beta = scal->beta * zt / scal->rz;
+        scal->rz = zt;
+    } else if (keep_dir && scal->rho > 0.0) {
+        beta = scal->beta * rt / scal->rho;
+    }
     scal->beta = beta;
     scal->rho = rt;
     scal->rho0 = rt;
@@ -382,15 +399,16 @@ __global__ void k_cg_group(CgScalars* scal, double threshold, int max_iter, int 
         scal->done = DONE_RUNNING;
 }
 
-hipError_t launch_cg_group(CgScalars* scal, double threshold, int max_iter, int keep_dir, hipStream_t s) {
+hipError_t launch_cg_group(CgScalars* scal, double threshold, int max_iter, int keep_dir, hipStream_t s,
+                           int precond) {
     ProfScope ps("cg_group", s);
-    k_cg_group<<<1, 64, 0, s>>>(scal, threshold, max_iter, keep_dir);
+    k_cg_group<<<1, 64, 0, s>>>(scal, threshold, max_iter, keep_dir, precond);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s) {
+hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s, int precond) {
     ProfScope ps("cg_setup", s);
-    k_cg_setup<<<1, 64, 0, s>>>(scal, rtol2, max_iter);
+    k_cg_setup<<<1, 64, 0, s>>>(scal, rtol2, max_iter, precond);
     return hipGetLastError();
 }
 

@@ -34,7 +34,9 @@ struct CgScalars {
     int max_iter;
     int pad0;
     int nblk;          // number of partials written by the last reduction kernel
-    int pad1;
+    int precond;       // 1: preconditioned CG (alpha, beta from <r, z>)
+    double rz;         // <r, z>, z = M^-1 r (preconditioned CG)
+    double dot2;       // second result slot of stand-alone dots
 };
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_BREAKDOWN = 2, DONE_MAXITER = 3 };
@@ -65,7 +67,9 @@ enum {
     POST_NONE = 0,   // nothing
     POST_DOT = 1,    // *out = total
     POST_ALPHA = 2,  // pq = total; alpha = rho / pq (breakdown if pq <= 0)
-    POST_RHO = 3     // rho1 = total; beta = rho1 / rho; rho = rho1; iters++; convergence test
+    POST_RHO = 3,    // rho1 = total; beta = rho1 / rho; rho = rho1; iters++; convergence test
+                     // (preconditioned: rho = total; iters++; convergence test only)
+    POST_RZ = 4      // preconditioned: rz1 = total; beta = rz1 / rz; rz = rz1
 };
 
 // Maximum grid of the reducing kernels (and size of the partials array).
@@ -116,11 +120,14 @@ hipError_t launch_cg_update(int tv, void* x, void* r, const void* p, const void*
 // that the fused tail pass has not applied yet when an iteration loop ends
 hipError_t launch_x_flush(int tv, void* x, const void* p, int64_t n, const CgScalars* scal,
                           hipStream_t s);
-// CG setup from device dots: threshold, rho, beta = 0, done flag
-hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s);
-// start of an iteration group after a reliable update (true <r, r> in scal->dot)
+// CG setup from device dots: threshold, rho, beta = 0, done flag; precond = 1
+// for the preconditioned iteration (scal->rz already holds <r, M^-1 r>)
+hipError_t launch_cg_setup(CgScalars* scal, double rtol2, int max_iter, hipStream_t s,
+                           int precond = 0);
+// start of an iteration group after a reliable update (true <r, r> in scal->dot,
+// and for the preconditioned iteration the true <r, z> in scal->dot2)
 hipError_t launch_cg_group(CgScalars* scal, double threshold, int max_iter, int keep_dir,
-                           hipStream_t s);
+                           hipStream_t s, int precond = 0);
 // padded copy of a (possibly transposed) device matrix in another dtype
 hipError_t launch_pad_matrix(int tin, int tout, const void* src, int rows, int cols, int trans,
                              void* dst, int rows_st, int ld, hipStream_t s);

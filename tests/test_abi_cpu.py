@@ -72,3 +72,15 @@ def test_cg_solve_rejects_null():
 def test_default_options():
     o = cta.cta_cg_opts_default()
     assert o["rtol"] == 1e-6 and o["check_every"] == 16 and o["precision"] == cta.PREC_F32
+
+
+def test_option_struct_matches_header():
+    """The binding's cta_cg_opts mirror has the C layout: the library's
+    default writer fills every field, including the last one."""
+    import ctypes
+    from paper_1001_5460_amd import _lib
+    o = _lib._CgOpts()
+    o.precond = 7
+    cta.load_library().cta_cg_opts_default(ctypes.byref(o))
+    assert o.precond == 0 and o.max_refine == 30
+    assert ctypes.sizeof(_lib._CgOpts) == 56
