@@ -183,6 +183,7 @@ cta_status cta_op_set_preconditioner(cta_op op, double c);
 cta_status cta_apply_precond(cta_op op, const void* R, void* Z, cta_dtype dtype, cta_precision chain,
                              double* dot, void* stream);
 
+
 /* ------------------------------------------------------------------------
  * Conjugate-gradient solve (Fig. Tensor_CG) of N(X) = B.
  *
@@ -237,6 +238,14 @@ void cta_cg_opts_default(cta_cg_opts* opts);
 
 cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype dtype,
                         const cta_cg_opts* opts, cta_cg_info* host_info, void* stream);
+/* Autotuner of the preconditioner strength: solves N(X) = B once per
+ * candidate c (host_c[0..count)) with `opts` (precond forced to 1, X
+ * overwritten) and keeps the preconditioner of the fastest solve that
+ * converged; its c goes to *best_c (host).  CTA_NOT_CONVERGED if no candidate
+ * converged (the preconditioner is then removed).  Synchronous. */
+cta_status cta_tune_preconditioner(cta_op op, const void* B, void* X, cta_dtype dtype,
+                                   const cta_cg_opts* opts, const double* host_c, int count,
+                                   double* best_c, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched solve: `count` independent problems of order 3 in one persistent

@@ -71,6 +71,9 @@ _SIGS = {
     "cta_apply_normal_op": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "cta_op_set_preconditioner": (ctypes.c_int, [_P, ctypes.c_double]),
     "cta_apply_precond": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "cta_tune_preconditioner": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(_CgOpts),
+                                               ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_double), _P]),
     "cta_cg_opts_default": (None, [ctypes.POINTER(_CgOpts)]),
     "cta_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(_CgOpts),
                                     ctypes.POINTER(_CgInfo), _P]),
@@ -304,6 +307,17 @@ def cta_apply_precond(h, R, Z, chain="f32", dot=None, stream=None):
     return Z
 
 
+def cta_tune_preconditioner(h, B, X, candidates, stream=None, **opts):
+    """Time one solve per strength c in ``candidates`` and keep the fastest; returns its c."""
+    o = _opts(**opts)
+    cs = (ctypes.c_double * len(candidates))(*[float(c) for c in candidates])
+    best = ctypes.c_double(-1.0)
+    _check(load_library().cta_tune_preconditioner(h, _dev(B, "B"), _dev(X, "X"), _dt(B), ctypes.byref(o),
+                                                  cs, len(candidates), ctypes.byref(best),
+                                                  _stream(stream)))
+    return best.value
+
+
 def cta_tune_op(h, chain="bf16", reps=5, stream=None):
     """Pick the fastest bit-identical tile shapes of the operator's passes; returns them."""
     lib = load_library()
@@ -497,6 +511,12 @@ class Operator:
 
     def set_preconditioner(self, c):
         cta_op_set_preconditioner(self.handle, c)
+
+    def tune_preconditioner(self, B, candidates, X=None, stream=None, **opts):
+        torch = _torch()
+        if X is None:
+            X = torch.empty_like(B)
+        return cta_tune_preconditioner(self.handle, B, X, candidates, stream, **opts)
 
     def precond(self, R, Z=None, chain="f32", dot=None, stream=None):
         torch = _torch()

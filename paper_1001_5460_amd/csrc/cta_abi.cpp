@@ -952,3 +952,31 @@ extern "C" cta_status cta_apply_precond(cta_op op, const void* R, void* Z, cta_d
         return fail(CTA_ERR_UNSUPPORTED, "operator chain not supported in this precision");
     return apply_precond(op, R, Z, chain, dot ? POST_DOT : POST_NONE, dot, false, (hipStream_t)stream);
 }
+
+extern "C" cta_status cta_tune_preconditioner(cta_op op, const void* B, void* X, cta_dtype dtype,
+                                              const cta_cg_opts* opts, const double* host_c, int count,
+                                              double* best_c, void* stream) {
+    if (!op || !B || !X || !opts || !host_c || !best_c) return fail(CTA_ERR_ARG, "NULL argument");
+    if (count < 1) return fail(CTA_ERR_ARG, "no candidates");
+    cta_cg_opts o = *opts;
+    o.precond = 1;
+    o.x0_given = 0;
+    double best = -1.0, best_s = 1e300;
+    for (int i = 0; i < count; ++i) {
+        if (!(host_c[i] >= 0)) return fail(CTA_ERR_ARG, "candidate %d is negative", i);
+        CTA_TRY(cta_op_set_preconditioner(op, host_c[i]));
+        cta_cg_info info;
+        const cta_status st = cta_cg_solve(op, B, X, dtype, &o, &info, stream);
+        if (st < 0 && st != CTA_ERR_BREAKDOWN) return st;
+        if (st == CTA_OK && info.seconds < best_s) {
+            best_s = info.seconds;
+            best = host_c[i];
+        }
+    }
+    *best_c = best;
+    if (best < 0) {
+        CTA_TRY(cta_op_set_preconditioner(op, -1.0));
+        return fail(CTA_NOT_CONVERGED, "no candidate strength converged");
+    }
+    return cta_op_set_preconditioner(op, best);
+}

@@ -102,3 +102,18 @@ def test_preconditioner_errors_and_removal():
     with pytest.raises(cta.CtaError):
         cta.cta_solve_batched([op.handle], [Bd], [torch.zeros_like(Bd)], precision="f32", rtol=1e-5,
                               precond=1)
+
+
+def test_tune_preconditioner_picks_a_converging_strength():
+    torch = torch_cuda()
+    p, ref, B = _setup((24, 20, 16, 12), 1e-3, seed=4)
+    op = cta.Operator(p.A, p.D, p.lam)
+    Bd = dev(B, torch.float64)
+    cands = [1e-3, 1.6e-2, 6.4e-2]
+    c = op.tune_preconditioner(Bd, cands, precision="bf16_reliable", rtol=1e-8, inner_rtol=0.1,
+                               max_iter=3000, max_refine=80)
+    assert c in cands
+    X, info = op.solve(Bd, precision="bf16_reliable", rtol=1e-8, inner_rtol=0.1, max_iter=3000,
+                       max_refine=80, precond=1)
+    assert info["status"] == 0
+    assert oracle.relative_residual(host(X), B, ref) <= 1.05e-8
