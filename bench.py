@@ -299,6 +299,9 @@ def main():
                     help="held-out seeds (from 10000) of the warm-start gain measurement")
     ap.add_argument("--no-warmstart", action="store_true",
                     help="skip the warm-start summary in the headline line")
+    ap.add_argument("--set-tuning", action="append", default=[],
+                    help="override the autotuner after it ran, e.g. bf16:0,1,2 (tail, middle, last "
+                         "variant of that chain precision); used to profile a fixed kernel set")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the tensor-inverse preconditioned solve in the headline line")
     ap.add_argument("--pc-inner-rtol", type=float, default=0.03,
@@ -358,6 +361,11 @@ def main():
     X = torch.empty(n, dtype=torch.float64, device=dev)
     # the autotuner picks the tile shapes of every pass (outside the timed region)
     tuning = {c: op.tune(c, reps=5) for c in ("bf16", "f64", "f32")}
+    for spec in args.set_tuning:
+        chain, vals = spec.split(":")
+        v = [int(x) for x in vals.split(",")]
+        cta.cta_op_set_tuning(op.handle, chain, *v)
+        tuning[chain] = {"tail": v[0], "middle": v[1], "last": v[2], "set_by": "--set-tuning"}
     torch.cuda.synchronize()
 
     def step():
