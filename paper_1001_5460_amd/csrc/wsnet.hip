@@ -613,7 +613,7 @@ extern "C" cta_status cta_ws_create(cta_ws* out, int order, const int64_t* n, in
         return fail(CTA_ERR_HIP, "device query failed");
     }
     w->conv_grid = prop.multiProcessorCount * 8;
-    w->wg_grid = prop.multiProcessorCount * 4;
+    w->wg_grid = prop.multiProcessorCount;  // one weight-gradient partial per CU: the fixed-order sum stays short
     w->pw_grid = prop.multiProcessorCount * 4;
     bool ok = true;
     ok &= (w->params = (float*)al(w->P * 4)) != nullptr;
