@@ -136,6 +136,74 @@ static hipError_t go_last(StridedArgs a, const StencilArgs<Tvec>& st, int* grid_
     return hipGetLastError();
 }
 
+// Row-block last pass (normal_last_jtile): FP32 vectors, tensor order 3 or 4.
+template <typename Tmid, typename Tc, int NF>
+__global__ __launch_bounds__(CTA_WG) void k_normal_last_js(StridedArgs a, StencilArgs<float> st, JsGeom gm,
+                                                           const int* done) {
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[4];
+    double dot = 0.0;
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    for (int64_t tile = lb; tile < a.ntiles; tile += gridDim.x)
+        normal_last_jtile<Tmid, Tc, NF>(a, tile, smem, st, gm, dot);
+    block_partial(dot, st.partials, red);
+}
+
+// Variant 4 applies when the shape allows it (see normal_last_jtile); returns
+// hipErrorNotSupported otherwise, and the caller falls back to variant 2.
+template <typename Tmid, typename Tc>
+static hipError_t go_last_js(StridedArgs a, const StencilArgs<float>& st, int* grid_out, const int* done,
+                             hipStream_t s) {
+    const int N = st.order;
+    if (N != 3 && N != 4) return hipErrorNotSupported;
+    const int nN = (int)st.ext[N - 1], nM = (int)st.ext[N - 2];
+    const int64_t sM = st.stride[N - 2];
+    constexpr int LV = 16 / sizeof(Tmid);
+    if (nN % 4 != 0 || sM != nN || a.trail % JS_TN != 0 || a.trail % LV != 0 || a.trail >= (int64_t(1) << 30) ||
+        (int64_t)a.K * a.trail >= (int64_t(1) << 31) || a.K > 256)
+        return hipErrorNotSupported;
+    JsGeom gm{};
+    gm.nN = nN;
+    gm.nM = nM;
+    gm.sM = (int)sM;
+    gm.H = 2 * nN;
+    gm.LDW = JS_TN + 2 * gm.H;
+    if (N == 4) {
+        gm.nF = (int)st.ext[1];
+        gm.sF = st.stride[1];
+        if (gm.sF % JS_TN != 0) return hipErrorNotSupported;
+    }
+    const int NF = N == 4 ? 1 : 0;
+    const size_t lds = js_lds_bytes<Tc>(a.kpad, gm.H, NF, nN, nM);
+    if (lds > 64 * 1024) return hipErrorNotSupported;
+    // tile order: the row blocks of a column tile first, column tiles plane-grouped
+    const int njb = (a.K + JS_JB - 1) / JS_JB;
+    a.ntt = a.trail / JS_TN;
+    a.ntiles = a.ntt * njb;
+    a.pgroup = 0;
+    if (N == 4 && gm.nF % 8 == 0) {
+        a.plane = gm.sF;
+        a.nplane = gm.nF;
+        a.pgroup = 8;
+    }
+    const int grid = (grid_for(a.ntiles, kMaxGrid) + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
+    *grid_out = grid;
+    hipError_t e;
+    if (NF) {
+        auto kern = k_normal_last_js<Tmid, Tc, 1>;
+        e = ensure_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        kern<<<grid, CTA_WG, lds, s>>>(a, st, gm, done);
+    } else {
+        auto kern = k_normal_last_js<Tmid, Tc, 0>;
+        e = ensure_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        kern<<<grid, CTA_WG, lds, s>>>(a, st, gm, done);
+    }
+    return hipGetLastError();
+}
+
 template <typename Tmid, typename Tvec, typename Tc>
 static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, int* grid,
                          const int* done, hipStream_t s, int variant) {
@@ -156,6 +224,16 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
                      &st.eshift[k]);
     }
     const int jt = (a.J + 15) / 16;
+    // variant 4: row blocks with the whole stencil staged in LDS (FP32
+    // vectors, order 3 or 4); falls back to variant 2 when the shape does not
+    // allow it
+    if (variant == 4) {
+        if constexpr (sizeof(Tvec) == 4) {
+            const hipError_t e = go_last_js<Tmid, Tc>(a, st, grid, done, s);
+            if (e != hipErrorNotSupported) return e;
+        }
+        variant = 2;
+    }
     // variants 2 and 3: 32-column tiles walked plane-fastest (groups of 8
     // planes, or all planes) along the second mode; fall back to variant 1
     // when the shape does not allow it

@@ -507,6 +507,232 @@ inline size_t normal_last_lds(int kpad, int K, int J, int nN) {
 }
 
 // ---------------------------------------------------------------------------
+// Last pass in row blocks (FP32 vectors, tensor order 3 or 4): a tile is 32
+// output rows x 32 columns, and everything the 17-point stencil reads is staged
+// in LDS with coalesced loads: P rows j0-2 .. j0+33 over the columns
+// t0-H .. t0+32+H with H = 2 n_N (the contiguous mode and the second-to-last
+// mode, whose stride is n_N), and for order 4 the four neighbour planes of the
+// second mode (t +- stride, +- 2 stride).  One epilogue item (4 columns of one
+// row) per thread, no gathers from memory.  The X tile (all K rows) is staged
+// once per row block; the row blocks of a column tile run consecutively, so
+// its re-reads come from L2.  The chain part and every stencil sum are formed
+// in the same order as normal_last_tile, so both give identical Q.
+constexpr int JS_JB = 32;  // output rows per tile
+constexpr int JS_TN = 32;  // columns per tile
+
+struct JsGeom {
+    int nN, nM, sM, H, LDW;  // contiguous extent, halo-mode extent and stride, halo, window pitch
+    int nF;                  // far-mode extent (order 4), 0 for order 3
+    int64_t sF;              // far-mode stride
+};
+
+template <typename Tc>
+__host__ __device__ inline size_t js_lds_bytes(int kpad, int H, int NF, int nN, int nM) {
+    const size_t xs = (size_t)JS_TN * (kpad + 16 / sizeof(Tc)) * sizeof(Tc);
+    const size_t qs = (size_t)JS_JB * (JS_TN + 4) * 4;
+    const size_t a = ((xs > qs ? xs : qs) + 15) / 16 * 16;
+    const size_t pw = (size_t)(JS_JB + 4) * (JS_TN + 2 * H) * 4;
+    const size_t pf = (size_t)NF * 4 * JS_JB * JS_TN * 4;
+    const size_t bands = (size_t)(JS_JB + nN + nM + 8) * 5 * 4;
+    return a + pw + pf + bands;
+}
+
+template <typename Tin, typename Tc, int NF>
+__device__ __forceinline__ void normal_last_jtile(const StridedArgs& a, int64_t tile, unsigned char* smem,
+                                                  const StencilArgs<float>& st, const JsGeom& gm,
+                                                  double& dot_acc) {
+    typedef MT<Tc> T;
+    typedef float __attribute__((ext_vector_type(4))) vt;
+    constexpr int TN = JS_TN, JB = JS_JB;
+    constexpr int VEC = T::VEC;
+    constexpr int LV = 16 / sizeof(Tin);
+    constexpr int LDQ = TN + 4;
+    constexpr int N = NF ? 4 : 3;
+    const int K = a.K;
+    const int trail = (int)a.trail;
+    const int njb = (K + JB - 1) / JB;
+    const int jblk = (int)(tile % njb);
+    const int j0 = jblk * JB;
+    const int t0 = (int)last_tile_col<TN>(a, tile / njb);
+    const int ldx = a.kpad + 16 / (int)sizeof(Tc);
+    const int H = gm.H, LDW = gm.LDW;
+    const size_t xs_bytes = (size_t)TN * ldx * sizeof(Tc);
+    const size_t qs_bytes = (size_t)JB * LDQ * 4;
+    const size_t a_bytes = ((xs_bytes > qs_bytes ? xs_bytes : qs_bytes) + 15) / 16 * 16;
+    Tc* Xs = reinterpret_cast<Tc*>(smem);
+    float* Qs = reinterpret_cast<float*>(smem);
+    float* Pw = reinterpret_cast<float*>(smem + a_bytes);
+    float* Pf = Pw + (size_t)(JB + 4) * LDW;
+    float* b1 = Pf + (size_t)NF * 4 * JB * TN;
+    float* bN = b1 + JB * 5;
+    float* bM = bN + gm.nN * 5;
+    float* bF = bM + gm.nM * 5;
+    const bool has1 = st.rband[0] != nullptr;
+    const bool hasN = st.rband[N - 1] != nullptr;
+    const bool hasM = st.rband[N - 2] != nullptr;
+    const bool hasF = NF && st.rband[1] != nullptr;
+    const Tin* __restrict__ X = reinterpret_cast<const Tin*>(a.X);
+    float* __restrict__ Q = reinterpret_cast<float*>(a.Y);
+    const float* __restrict__ P = st.P;
+    const Tc* __restrict__ M = reinterpret_cast<const Tc*>(a.M);
+    // plane index of the tile along the far mode (TN divides its stride)
+    const int iF = NF ? (int)((t0 / gm.sF) % gm.nF) : 0;
+
+    // ---- stage the X tile (all K rows, transposed, Tc) ----
+    {
+        constexpr int TCH = TN / LV;
+        const int nunits = (a.kpad / VEC) * TCH;
+        for (int u = threadIdx.x; u < nunits; u += CTA_WG) {
+            const int tc = u % TCH;
+            const int kg = u / TCH;
+            const int t = t0 + tc * LV;
+            Tin v[VEC][LV];
+#pragma unroll
+            for (int r = 0; r < VEC; ++r) {
+                const int k = kg * VEC + r;
+                typedef Tin __attribute__((ext_vector_type(LV))) vin;
+                if (k < K) {
+                    const vin x = *reinterpret_cast<const vin*>(X + (int64_t)k * trail + t);
+#pragma unroll
+                    for (int c = 0; c < LV; ++c) v[r][c] = x[c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < LV; ++c) v[r][c] = cvt<Tin>(0.f);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < LV; ++c) {
+                typename T::frag f;
+#pragma unroll
+                for (int r = 0; r < VEC; ++r) f[r] = cvt<Tc>(v[r][c]);
+                *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
+            }
+        }
+    }
+    // ---- stage the P window (rows j0-2 .. j0+JB+1, zero outside the tensor) ----
+    {
+        const int cpr = LDW / 4;
+        for (int u = threadIdx.x; u < (JB + 4) * cpr; u += CTA_WG) {
+            const int r = u / cpr, ch = u - r * cpr;
+            const int j = j0 - 2 + r;
+            const int t = t0 - H + ch * 4;
+            vt v = {0.f, 0.f, 0.f, 0.f};
+            if (j >= 0 && j < K && t >= 0 && t < trail) v = *reinterpret_cast<const vt*>(P + (int64_t)j * trail + t);
+            *reinterpret_cast<vt*>(Pw + r * LDW + ch * 4) = v;
+        }
+    }
+    // ---- stage the far-mode neighbour planes (order 4) ----
+    if constexpr (NF) {
+        constexpr int cpr = TN / 4;
+        for (int u = threadIdx.x; u < 4 * JB * cpr; u += CTA_WG) {
+            const int q = u / (JB * cpr), rem = u - q * (JB * cpr);
+            const int r = rem / cpr, ch = rem - r * cpr;
+            const int d = q < 2 ? q - 2 : q - 1;
+            const int j = j0 + r;
+            vt v = {0.f, 0.f, 0.f, 0.f};
+            if (j < K && iF + d >= 0 && iF + d < gm.nF)
+                v = *reinterpret_cast<const vt*>(P + (int64_t)j * trail + t0 + (int64_t)d * gm.sF + ch * 4);
+            *reinterpret_cast<vt*>(Pf + (q * JB + r) * TN + ch * 4) = v;
+        }
+    }
+    // ---- band coefficients ----
+    for (int u = threadIdx.x; u < JB * 5; u += CTA_WG) {
+        const int j = j0 + u / 5;
+        b1[u] = (has1 && j < K) ? st.rband[0][j * 5 + u % 5] : 0.f;
+    }
+    if (hasN)
+        for (int u = threadIdx.x; u < gm.nN * 5; u += CTA_WG) bN[u] = st.rband[N - 1][u];
+    if (hasM)
+        for (int u = threadIdx.x; u < gm.nM * 5; u += CTA_WG) bM[u] = st.rband[N - 2][u];
+    if (hasF && threadIdx.x < 5) bF[threadIdx.x] = st.rband[1][iF * 5 + threadIdx.x];
+    __syncthreads();
+
+    // ---- MFMA: wave w computes rows j0 + 16 (w >> 1) .. +16, columns 16 (w & 1) .. +16 ----
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int g = lane >> 4, l16 = lane & 15;
+        const int jr = (wave >> 1) * 16, cb = (wave & 1) * 16;
+        typename T::acc acc = T::zero();
+        const int nks = a.kpad / T::KSTEP;
+        for (int ks = 0; ks < nks; ++ks) {
+            const int k0 = ks * T::KSTEP + VEC * g;
+            const typename T::frag xa = *reinterpret_cast<const typename T::frag*>(Xs + (cb + l16) * ldx + k0);
+            const typename T::frag mb = *reinterpret_cast<const typename T::frag*>(
+                M + (int64_t)(j0 + jr + l16) * a.ldm + k0);
+            acc = T::mma(xa, mb, acc);
+        }
+        __syncthreads();  // Xs is dead; its space becomes Qs
+        vt o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = acc[r];
+        *reinterpret_cast<vt*>(Qs + (jr + l16) * LDQ + cb + 4 * g) = o;
+    }
+    __syncthreads();
+
+    // ---- epilogue: one item (4 columns of one row) per thread ----
+    {
+        const float lam = (float)st.lam;
+        const int it = threadIdx.x;
+        const int jr = it >> 3, c = (it & 7) * 4;
+        const int j = j0 + jr;
+        const int t = t0 + c;
+        if (j < K) {
+            const float* prow = Pw + (jr + 2) * LDW + H + c;  // prow[0] is P[j][t]
+            const vt pc = *reinterpret_cast<const vt*>(prow);
+            const vt s = *reinterpret_cast<const vt*>(Qs + jr * LDQ + c);
+            vt reg = {0.f, 0.f, 0.f, 0.f};
+            if (has1) {
+#pragma unroll
+                for (int d = -2; d <= 2; ++d)
+                    reg += b1[jr * 5 + d + 2] * *reinterpret_cast<const vt*>(prow + d * LDW);
+            }
+            if (hasN) {
+                float w[12];
+                const vt pl = *reinterpret_cast<const vt*>(prow - 4);
+                const vt pr = *reinterpret_cast<const vt*>(prow + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    w[e] = pl[e];
+                    w[4 + e] = pc[e];
+                    w[8 + e] = pr[e];
+                }
+                const int i0 = t - fast_div(t, st.emul[N - 1], st.eshift[N - 1]) * gm.nN;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float* bb = bN + (i0 + e) * 5;
+#pragma unroll
+                    for (int d = -2; d <= 2; ++d) reg[e] += bb[d + 2] * w[4 + e + d];
+                }
+            }
+            if constexpr (NF) {
+                if (hasF) {
+                    reg += bF[2] * pc;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        reg += bF[q < 2 ? q : q + 1] * *reinterpret_cast<const vt*>(Pf + (q * JB + jr) * TN + c);
+                }
+            }
+            if (hasM) {
+                const int u = fast_div(t, st.smul[N - 2], st.sshift[N - 2]);
+                const int iM = u - fast_div(u, st.emul[N - 2], st.eshift[N - 2]) * gm.nM;
+                const float* br = bM + iM * 5;
+                reg += br[2] * pc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int d = q < 2 ? q - 2 : q - 1;
+                    reg += br[q < 2 ? q : q + 1] * *reinterpret_cast<const vt*>(prow + d * gm.sM);
+                }
+            }
+            const vt qv = s + lam * reg;
+            *reinterpret_cast<vt*>(Q + (int64_t)j * trail + t) = qv;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dot_acc += (double)pc[e] * (double)qv[e];
+        }
+    }
+    __syncthreads();  // LDS is reused by the next tile
+}
+
+// ---------------------------------------------------------------------------
 // Tail pass on groups of `nb` consecutive blocks of the last two modes.  J2T:
 // maximum number of 16-wide j2 tiles (compile time); the runtime count is
 // (J2 + 15) / 16.  LDS: Zt for every block of the group, then the output

@@ -106,7 +106,8 @@ def test_unsupported_wide_regulariser():
 
 @pytest.mark.parametrize("chain", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("n,m", [((16, 12, 10, 8), (24, 18, 15, 12)), ((32, 32, 32), (48, 48, 48)),
-                                 ((40, 24, 20, 16), (60, 36, 30, 24))])
+                                 ((40, 24, 20, 16), (60, 36, 30, 24)),
+                                 ((72, 32, 24, 16), (108, 48, 36, 24))])
 def test_tile_variants_match_oracle(n, m, chain):
     torch = torch_cuda()
     p, ref_op = _op(n, m, 1e-3)
@@ -115,8 +116,8 @@ def test_tile_variants_match_oracle(n, m, chain):
     P = dev(np.random.default_rng(11).standard_normal(n), dt)
     ref = ref_op(host(P))
     outs = []
-    for combo in range(16):
-        cta.cta_op_set_tuning(op.handle, chain, combo & 1, (combo >> 1) & 1, (combo >> 2) & 3)
+    for combo in range(20):
+        cta.cta_op_set_tuning(op.handle, chain, combo & 1, (combo >> 1) & 1, combo >> 2)
         Q = op.apply(P, chain=chain)
         torch.cuda.synchronize()
         assert rel_fro(host(Q), ref) <= TOL[chain]
