@@ -163,10 +163,12 @@ cta_status cta_apply_normal_op(cta_op op, const void* P, void* Q, cta_dtype dtyp
 cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
 /* The variants chosen for `chain` (tail, middle, last pass) into host_variants3;
  * cta_op_set_tuning sets them: tail and middle 0 or 1 (tile shape), last
- * 0..4 (0, 1: tile shape; 2, 3: the narrow shape with its tiles walked
+ * 0..5 (0, 1: tile shape; 2, 3: the narrow shape with its tiles walked
  * along the second mode first, in groups of 8 planes or all planes; 4: row
  * blocks of 32 with the whole stencil staged on chip, F32/BF16 chains of
- * order 3 or 4, else as 2). */
+ * order 3 or 4, else as 2; 5: persistent workgroups that load the next
+ * tile while computing the current one, BF16 chains with 96 < n_1 <= 128,
+ * else as 2). */
 cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3);
 cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3);
 

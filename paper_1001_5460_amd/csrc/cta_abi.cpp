@@ -805,10 +805,10 @@ extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void
     CTA_HIP(hipEventCreate(&e1));
     int best[3] = {0, 0, 0};
     float best_ms = 1e30f;
-    // tail and middle passes: 2 tile shapes each; last pass: 5 (two tile
-    // shapes, two plane-grouped tile orders of the narrow one, and row blocks
-    // with the whole stencil in LDS)
-    for (int combo = 0; combo < 20; ++combo) {
+    // tail and middle passes: 2 tile shapes each; last pass: 6 (two tile
+    // shapes, two plane-grouped tile orders of the narrow one, row blocks with
+    // the whole stencil in LDS, and the persistent pipelined form)
+    for (int combo = 0; combo < 24; ++combo) {
         op->var_tail[tc] = combo & 1;
         op->var_mid[tc] = (combo >> 1) & 1;
         op->var_last[tc] = combo >> 2;
@@ -860,8 +860,8 @@ extern "C" cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* hos
 extern "C" cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3) {
     if (!op || !host_variants3) return fail(CTA_ERR_ARG, "NULL argument");
     for (int i = 0; i < 3; ++i)
-        if (host_variants3[i] < 0 || host_variants3[i] > (i == 2 ? 4 : 1))
-            return fail(CTA_ERR_ARG, "variants must be 0 or 1 (tail, middle) and 0..4 (last)");
+        if (host_variants3[i] < 0 || host_variants3[i] > (i == 2 ? 5 : 1))
+            return fail(CTA_ERR_ARG, "variants must be 0 or 1 (tail, middle) and 0..5 (last)");
     const int tc = prec_tc(chain);
     op->var_tail[tc] = host_variants3[0];
     op->var_mid[tc] = host_variants3[1];

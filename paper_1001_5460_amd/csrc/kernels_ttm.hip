@@ -136,6 +136,58 @@ static hipError_t go_last(StridedArgs a, const StencilArgs<Tvec>& st, int* grid_
     return hipGetLastError();
 }
 
+// Pipelined persistent last pass (normal_last_pipe): BF16 chain, FP32 vectors,
+// 96 < K <= 128.
+__global__ __launch_bounds__(CTA_WG) void k_normal_last_pipe(StridedArgs a, StencilArgs<float> st,
+                                                             const int* done) {
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[4];
+    double dot = 0.0;
+    normal_last_pipe(a, smem, st, dot, xcd_logical_block(blockIdx.x, gridDim.x), gridDim.x);
+    block_partial(dot, st.partials, red);
+}
+
+static int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+    }
+    return cus;
+}
+
+static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int* grid_out, const int* done,
+                               hipStream_t s) {
+    const int N = st.order;
+    const int nN = (int)st.ext[N - 1];
+    if (a.kpad != 128 || a.K != a.J || a.trail % PIPE_TN != 0 || nN % 4 != 0 || a.trail >= (int64_t(1) << 30))
+        return hipErrorNotSupported;
+    a.ntt = a.trail / PIPE_TN;
+    a.ntiles = a.ntt;
+    a.pgroup = 0;
+    const int64_t plane = N >= 3 ? st.stride[1] : 0;
+    const int nplane = N >= 3 ? (int)st.ext[1] : 0;
+    if (plane > 0 && plane % PIPE_TN == 0 && nplane % 8 == 0 && plane * nplane == a.trail) {
+        a.plane = plane;
+        a.nplane = nplane;
+        a.pgroup = 8;
+    }
+    const size_t xq = std::max<size_t>((size_t)PIPE_TN * (128 + 8) * 2, (size_t)128 * (PIPE_TN + 4) * 4);
+    const size_t lds = (xq + 15) / 16 * 16 + (size_t)128 * PIPE_LDP * 4 + (size_t)(128 + nN) * 5 * 4;
+    if (lds > 64 * 1024) return hipErrorNotSupported;
+    // persistent grid: three workgroups per CU, a multiple of the XCD count
+    int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);
+    grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
+    *grid_out = grid;
+    hipError_t e = ensure_lds(k_normal_last_pipe, lds);
+    if (e != hipSuccess) return e;
+    k_normal_last_pipe<<<grid, CTA_WG, lds, s>>>(a, st, done);
+    return hipGetLastError();
+}
+
 // Row-block last pass (normal_last_jtile): FP32 vectors, tensor order 3 or 4.
 template <typename Tmid, typename Tc, int NF>
 __global__ __launch_bounds__(CTA_WG) void k_normal_last_js(StridedArgs a, StencilArgs<float> st, JsGeom gm,
@@ -230,6 +282,14 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
     if (variant == 4) {
         if constexpr (sizeof(Tvec) == 4) {
             const hipError_t e = go_last_js<Tmid, Tc>(a, st, grid, done, s);
+            if (e != hipErrorNotSupported) return e;
+        }
+        variant = 2;
+    }
+    // variant 5: persistent and pipelined (BF16 chains, 96 < K <= 128)
+    if (variant == 5) {
+        if constexpr (sizeof(Tvec) == 4 && sizeof(Tc) == 2) {
+            const hipError_t e = go_last_pipe(a, st, grid, done, s);
             if (e != hipErrorNotSupported) return e;
         }
         variant = 2;

@@ -507,6 +507,228 @@ inline size_t normal_last_lds(int kpad, int K, int J, int nN) {
 }
 
 // ---------------------------------------------------------------------------
+// Pipelined form of normal_last_tile for BF16 chains with FP32 vectors, 32
+// columns per tile, persistent workgroups: the global loads of the next tile
+// (its X tile, two 16-byte rows per thread, and its P window) are issued into
+// registers before the current tile's MFMA and epilogue and written to LDS
+// after them, so they are in flight while the current tile computes.  The
+// band coefficients are staged once per workgroup.  Same sums in the same
+// order as normal_last_tile (identical Q).
+struct PipeRegs {
+    bf16x8 x[2];        // rows 2 kp, 2 kp + 1 of the X tile, 8 columns
+    floatx4 p[5];       // P window chunks owned by this thread (K <= 128 rows x 10 chunks)
+};
+
+constexpr int PIPE_TN = 32;
+constexpr int PIPE_H = 4;
+constexpr int PIPE_LDP = PIPE_TN + 2 * PIPE_H;   // 40 floats: 10 chunks of 4 per row
+
+template <int KPAD>
+__device__ __forceinline__ void pipe_load(const StridedArgs& a, const float* __restrict__ P, int t0, int K,
+                                          PipeRegs& r) {
+    const bf16* __restrict__ X = reinterpret_cast<const bf16*>(a.X);
+    const int trail = (int)a.trail;
+    // X: unit = (row pair kp, column group cg of 8), cg fastest so that 4 lanes read a row's 64 bytes
+    {
+        const int cg = threadIdx.x & 3, kp = threadIdx.x >> 2;  // kp < 64 covers K <= 128
+        const int t = t0 + cg * 8;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = 2 * kp + h;
+            bf16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (bf16)0.f;
+            if (k < K) v = *reinterpret_cast<const bf16x8*>(X + (int64_t)k * trail + t);
+            r.x[h] = v;
+        }
+    }
+    // P window: K rows x 10 chunks of 4 floats, chunk u = threadIdx.x + 256 i
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const int u = threadIdx.x + CTA_WG * i;
+        const int row = u / 10, ch = u - row * 10;
+        const int t = t0 - PIPE_H + ch * 4;
+        floatx4 v = {0.f, 0.f, 0.f, 0.f};
+        if (row < K && t >= 0 && t < trail) v = *reinterpret_cast<const floatx4*>(P + (int64_t)row * trail + t);
+        r.p[i] = v;
+    }
+}
+
+template <int KPAD>
+__device__ __forceinline__ void pipe_store(const PipeRegs& r, bf16* Xs, float* Pw, int K) {
+    constexpr int ldx = KPAD + 8;
+    {
+        const int cg = threadIdx.x & 3, kp = threadIdx.x >> 2;
+        if (2 * kp < KPAD) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                typedef bf16 __attribute__((ext_vector_type(2))) bf16x2;
+                bf16x2 pr;
+                pr[0] = r.x[0][c];
+                pr[1] = r.x[1][c];
+                *reinterpret_cast<bf16x2*>(Xs + (cg * 8 + c) * ldx + 2 * kp) = pr;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const int u = threadIdx.x + CTA_WG * i;
+        const int row = u / 10, ch = u - row * 10;
+        if (row < K) *reinterpret_cast<floatx4*>(Pw + row * PIPE_LDP + ch * 4) = r.p[i];
+    }
+}
+
+// Persistent, pipelined last pass (see PipeRegs); K <= 128, kpad == 128.
+__device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned char* smem,
+                                                 const StencilArgs<float>& st, double& dot_acc,
+                                                 int64_t first, int64_t step) {
+    typedef MT<bf16> T;
+    typedef float Tv;
+    typedef floatx4 vt;
+    constexpr int KPAD = 128;
+    constexpr int TN = PIPE_TN, H = PIPE_H, LDP = PIPE_LDP;
+    constexpr int E = 4, LDQ = TN + E, VEC = T::VEC;
+    constexpr int ldx = KPAD + 8;
+    constexpr int JT = 2, CT = 2;
+    const int K = a.K;
+    const int trail = (int)a.trail;
+    const int N = st.order;
+    const int nN = (int)st.ext[N - 1];
+    constexpr size_t a_bytes = ((size_t)(TN * ldx * 2) > (size_t)(KPAD * LDQ * 4) ? (size_t)(TN * ldx * 2)
+                                                                                    : (size_t)(KPAD * LDQ * 4));
+    bf16* Xs = reinterpret_cast<bf16*>(smem);
+    float* Qs = reinterpret_cast<float*>(smem);
+    float* Pw = reinterpret_cast<float*>(smem + (a_bytes + 15) / 16 * 16);
+    float* band1 = Pw + (size_t)KPAD * LDP;
+    float* bandN = band1 + (size_t)KPAD * 5;
+    const bool has1 = st.rband[0] != nullptr;
+    const bool hasN = st.rband[N - 1] != nullptr;
+    float* __restrict__ Q = reinterpret_cast<float*>(a.Y);
+    const float* __restrict__ P = st.P;
+    const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
+    if (has1)
+        for (int u = threadIdx.x; u < K * 5; u += CTA_WG) band1[u] = st.rband[0][u];
+    if (hasN)
+        for (int u = threadIdx.x; u < nN * 5; u += CTA_WG) bandN[u] = st.rband[N - 1][u];
+    PipeRegs r;
+    if (first < a.ntiles) pipe_load<KPAD>(a, P, (int)last_tile_col<TN>(a, first), K, r);
+    const Tv lam = (Tv)st.lam;
+    for (int64_t tile = first; tile < a.ntiles; tile += step) {
+        const int t0 = (int)last_tile_col<TN>(a, tile);
+        pipe_store<KPAD>(r, Xs, Pw, K);
+        __syncthreads();
+        if (tile + step < a.ntiles) pipe_load<KPAD>(a, P, (int)last_tile_col<TN>(a, tile + step), K, r);
+        // ---- MFMA (as normal_last_tile with JT = 2, WJ = 4, CT = 2) ----
+        {
+            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            const int jb = wave * JT * 16;
+            const int g = lane >> 4, l16 = lane & 15;
+            typename T::acc acc[JT][CT];
+#pragma unroll
+            for (int x = 0; x < JT; ++x)
+#pragma unroll
+                for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
+            for (int ks = 0; ks < KPAD / T::KSTEP; ++ks) {
+                const int k0 = ks * T::KSTEP + VEC * g;
+                typename T::frag xa[CT], mb[JT];
+#pragma unroll
+                for (int y = 0; y < CT; ++y)
+                    xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (y * 16 + l16) * ldx + k0);
+#pragma unroll
+                for (int x = 0; x < JT; ++x)
+                    mb[x] = *reinterpret_cast<const typename T::frag*>(M + (int64_t)(jb + x * 16 + l16) * a.ldm + k0);
+#pragma unroll
+                for (int x = 0; x < JT; ++x)
+#pragma unroll
+                    for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
+            }
+            __syncthreads();  // Xs is dead; its space becomes Qs
+#pragma unroll
+            for (int x = 0; x < JT; ++x) {
+                const int j = jb + x * 16 + l16;
+                if (j >= a.J) continue;
+#pragma unroll
+                for (int y = 0; y < CT; ++y) {
+                    vt o;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) o[q] = acc[x][y][q];
+                    *reinterpret_cast<vt*>(Qs + j * LDQ + y * 16 + 4 * g) = o;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- epilogue (the fast path of normal_last_tile) ----
+        constexpr int GPR = TN / E;
+#pragma unroll 1
+        for (int it = threadIdx.x; it < a.J * GPR; it += CTA_WG) {
+            const int j = it / GPR;
+            const int c = (it - j * GPR) * E;
+            const int t = t0 + c;
+            if (t >= trail) continue;
+            const Tv* prow = Pw + j * LDP + H + c;  // prow[0] is P[j][t]
+            const int64_t base = (int64_t)j * trail + t;
+            // Branch-free taps: a tap outside the tensor has a zero band
+            // coefficient (R_k[i][i+d] with i+d out of range is stored as 0), so
+            // its address is clamped to a valid one instead of tested.
+            const vt pc = *reinterpret_cast<const vt*>(prow);
+            vt s = *reinterpret_cast<const vt*>(Qs + j * LDQ + c);  // chain part, lam applied below
+            vt reg;
+#pragma unroll
+            for (int e = 0; e < E; ++e) reg[e] = Tv(0);
+            if (has1) {
+#pragma unroll
+                for (int d = -2; d <= 2; ++d) {
+                    const int jj = min(max(j + d, 0), K - 1);
+                    reg += band1[j * 5 + d + 2] * *reinterpret_cast<const vt*>(Pw + jj * LDP + H + c);
+                }
+            }
+            if (hasN) {
+                Tv w[3 * E];
+                const vt pl = *reinterpret_cast<const vt*>(prow - E);
+                const vt pr = *reinterpret_cast<const vt*>(prow + E);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    w[e] = pl[e];
+                    w[E + e] = pc[e];
+                    w[2 * E + e] = pr[e];
+                }
+                const int i0 = t - fast_div(t, st.emul[N - 1], st.eshift[N - 1]) * nN;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const Tv* bN = bandN + (i0 + e) * 5;
+#pragma unroll
+                    for (int d = -2; d <= 2; ++d) reg[e] += bN[d + 2] * w[E + e + d];
+                }
+            }
+            const Tv* __restrict__ pb = P + base;
+            for (int k = 1; k < N - 1; ++k) {
+                const Tv* __restrict__ rb = st.rband[k];
+                if (!rb) continue;
+                const int sk = (int)st.stride[k], nk = (int)st.ext[k];
+                const int u = fast_div(t, st.smul[k], st.sshift[k]);
+                const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
+                const Tv* br = rb + ik * 5;
+                vt nbv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
+                    const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
+                    nbv[q] = *reinterpret_cast<const vt*>(pb + dd * sk);
+                }
+                reg += br[2] * pc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) reg += br[q < 2 ? q : q + 1] * nbv[q];
+            }
+            const vt qv = s + lam * reg;
+            *reinterpret_cast<vt*>(Q + base) = qv;
+#pragma unroll
+            for (int e = 0; e < E; ++e) dot_acc += (double)pc[e] * (double)qv[e];
+        }
+        __syncthreads();  // LDS is reused by the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Last pass in row blocks (FP32 vectors, tensor order 3 or 4): a tile is 32
 // output rows x 32 columns, and everything the 17-point stencil reads is staged
 // in LDS with coalesced loads: P rows j0-2 .. j0+33 over the columns

@@ -107,7 +107,8 @@ def test_unsupported_wide_regulariser():
 @pytest.mark.parametrize("chain", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("n,m", [((16, 12, 10, 8), (24, 18, 15, 12)), ((32, 32, 32), (48, 48, 48)),
                                  ((40, 24, 20, 16), (60, 36, 30, 24)),
-                                 ((72, 32, 24, 16), (108, 48, 36, 24))])
+                                 ((72, 32, 24, 16), (108, 48, 36, 24)),
+                                 ((112, 16, 12, 8), (168, 24, 18, 12))])
 def test_tile_variants_match_oracle(n, m, chain):
     torch = torch_cuda()
     p, ref_op = _op(n, m, 1e-3)
@@ -116,7 +117,7 @@ def test_tile_variants_match_oracle(n, m, chain):
     P = dev(np.random.default_rng(11).standard_normal(n), dt)
     ref = ref_op(host(P))
     outs = []
-    for combo in range(20):
+    for combo in range(24):
         cta.cta_op_set_tuning(op.handle, chain, combo & 1, (combo >> 1) & 1, combo >> 2)
         Q = op.apply(P, chain=chain)
         torch.cuda.synchronize()
