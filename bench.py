@@ -450,7 +450,10 @@ def main():
         try:
             with open(TRAFFIC_FILE) as f:
                 tj = json.load(f)
-            if tj.get("kernel") == dom:
+            # only for the same kernel and the same pass variants as this run
+            tv = tuning.get("bf16", {})
+            same = all(tj.get("tuning", {}).get(k) == tv.get(k) for k in ("tail", "middle", "last"))
+            if tj.get("kernel") == dom and same:
                 traffic = tj.get("traffic_bytes_per_launch")
         except Exception:
             traffic = None

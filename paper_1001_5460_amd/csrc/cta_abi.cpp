@@ -684,6 +684,7 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
             // One CG over the BF16 chain; vx holds the FP32 correction since the
             // last reliable update, vp the search direction kept across updates.
             const double target = rtol * rtol * bn2;
+            const bool f32_ok = tail_fits(DT_F32, (int)op->n[N - 2], (int)op->n[N - 1]);
             CTA_HIP(launch_fill_zero(op->vx, (size_t)n * 4, s));
             CTA_HIP(launch_fill_zero(op->vp, (size_t)n * 4, s));
             while (true) {
@@ -725,13 +726,25 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
                     done = DONE_BREAKDOWN;
                     break;
                 }
-                // reliable update: X64 += vx, vx = 0, r = B - N64(X64)
+                // reliable update: X64 += vx, vx = 0, r = B - N(X64).  While the new
+                // residual is expected above 1e-4 ||B|| (eta^2 times the last one), the
+                // FP32 chain's error (~1e-6 ||B||) is below 1% of it and N(X) is formed
+                // in FP32; the updates close to the tolerance use the FP64 chain.
                 CTA_HIP(launch_add_f64((double*)X, op->vx, DT_F32, n, s));
-                CTA_HIP(launch_fill_zero(op->vx, (size_t)n * 4, s));
                 ++steps;
-                CTA_TRY(apply_normal(op, X, op->vq, CTA_PREC_F64, POST_NONE, nullptr, false, s));
-                CTA_HIP(launch_residual(DT_F64, DT_F32, B, op->vq, op->vr, n, op->partials, op->scal,
-                                        &op->scal->dot, s));
+                const bool f32_update = eta * eta * rr > 1e-8 * bn2 && f32_ok;
+                if (f32_update) {
+                    CTA_HIP(launch_cast(DT_F64, DT_F32, X, op->vx, n, s));
+                    CTA_TRY(apply_normal(op, op->vx, op->vq, CTA_PREC_F32, POST_NONE, nullptr, false, s));
+                    CTA_HIP(launch_residual_mixed((const double*)B, (const float*)op->vq, (float*)op->vr, n,
+                                                  op->partials, op->scal, &op->scal->dot, s));
+                    CTA_HIP(launch_fill_zero(op->vx, (size_t)n * 4, s));
+                } else {
+                    CTA_HIP(launch_fill_zero(op->vx, (size_t)n * 4, s));
+                    CTA_TRY(apply_normal(op, X, op->vq, CTA_PREC_F64, POST_NONE, nullptr, false, s));
+                    CTA_HIP(launch_residual(DT_F64, DT_F32, B, op->vq, op->vr, n, op->partials, op->scal,
+                                            &op->scal->dot, s));
+                }
                 CTA_TRY(read_scal(op, s));
                 rr = op->hscal->dot;
                 if (gdone == DONE_BREAKDOWN) {

@@ -184,22 +184,22 @@ hipError_t launch_finalize(const double* partials, int n, CgScalars* scal, int p
 }
 
 // ------------------------------------------------------------------ residual r = B - Q, <r, r>
-template <typename Tb, typename Tr>
+template <typename Tb, typename Tr, typename Tq = Tb>
 __global__ __launch_bounds__(CTA_WG) void k_residual(const Tb* __restrict__ B,
-                                                     const Tb* __restrict__ Q, Tr* __restrict__ r,
+                                                     const Tq* __restrict__ Q, Tr* __restrict__ r,
                                                      int64_t n, double* partials) {
     __shared__ double red[4];
     double acc = 0.0;
     CTA_SWEEP(n,
               {
                   for (int u = 0; u < kItems; ++u) {
-                      const Tr v = cvt<Tr>(B[i + u] - Q[i + u]);
+                      const Tr v = cvt<Tr>(B[i + u] - (Tb)Q[i + u]);
                       r[i + u] = v;
                       acc += (double)v * (double)v;
                   }
               },
               {
-                  const Tr v = cvt<Tr>(B[e] - Q[e]);
+                  const Tr v = cvt<Tr>(B[e] - (Tb)Q[e]);
                   r[e] = v;
                   acc += (double)v * (double)v;
               })
@@ -222,6 +222,19 @@ hipError_t launch_residual(int tb, int tr, const void* B, const void* Q, void* r
                                                           (float*)r, n, partials);
         else
             return hipErrorInvalidValue;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_finalize(partials, g, scal, POST_DOT, out, s);
+}
+
+// r = B - Q with B in FP64 and Q in FP32, r stored in FP32, <r, r> reduced
+hipError_t launch_residual_mixed(const double* B, const float* Q, float* r, int64_t n, double* partials,
+                                 CgScalars* scal, double* out, hipStream_t s) {
+    const int g = red_grid(n);
+    {
+        ProfScope ps("residual.f64_f32q", s);
+        k_residual<double, float, float><<<g, CTA_WG, 0, s>>>(B, Q, r, n, partials);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -109,6 +109,9 @@ hipError_t launch_axpby(int tv, double a, const void* x, double b, void* y, int6
 // r = B - Q (tb: dtype of B and Q; tr: dtype of r); returns <r, r> into scal->rho via reduction
 hipError_t launch_residual(int tb, int tr, const void* B, const void* Q, void* r, int64_t n,
                            double* partials, CgScalars* scal, double* out, hipStream_t s);
+// r = B - Q for FP64 B and FP32 Q, r in FP32; <r, r> into *out
+hipError_t launch_residual_mixed(const double* B, const float* Q, float* r, int64_t n, double* partials,
+                                 CgScalars* scal, double* out, hipStream_t s);
 // out = <x, y> (FP64, deterministic two-stage reduction)
 hipError_t launch_dot(int tv, const void* x, const void* y, int64_t n, double* partials,
                       CgScalars* scal, double* out, hipStream_t s);
