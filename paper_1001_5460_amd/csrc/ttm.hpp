@@ -106,6 +106,139 @@ struct ContigArgs {
 };
 
 // ---------------------------------------------------------------------------
+// Stage columns [t0, t0 + TN) of a row-major K x ncol slab X (row pitch
+// `pitch` elements) into LDS transposed, Xs[c * ldx + k] in Tc; rows K..kpad-1
+// and columns at or past ncol are zero.  A unit is VEC rows x LV columns (one
+// 16-byte load per row).  Interior tiles take a branch-free path: row and unit
+// indices are clamped so every address is valid, the loads of UB units are
+// issued before the first LDS write, and out-of-range values are replaced by
+// zero afterwards, so a thread keeps UB * VEC loads in flight instead of one
+// (units past the last whole batch of UB * CTA_WG go one at a time).
+template <typename Tin, typename Tc, int TN>
+__device__ __forceinline__ void stage_cols(const Tin* __restrict__ X, int64_t pitch, int K,
+                                           int kpad, int64_t t0, int64_t ncol, Tc* Xs, int ldx) {
+    typedef MT<Tc> T;
+    constexpr int VEC = T::VEC;
+    constexpr int LV = 16 / sizeof(Tin);
+    constexpr int TCH = TN / LV;  // 16-byte chunks per slab row
+    constexpr int UB = 4;
+    typedef Tin __attribute__((ext_vector_type(LV))) vin;
+    const int nunits = (kpad / VEC) * TCH;
+    if ((pitch % LV) == 0 && t0 + TN <= ncol) {
+        const Tin* __restrict__ Xt = X + t0;
+        // whole batches: every unit valid, no branch between loads and stores
+        const int nfull = nunits / (CTA_WG * UB) * (CTA_WG * UB);
+        for (int u0 = threadIdx.x; u0 < nfull; u0 += CTA_WG * UB) {
+            vin v[UB][VEC];
+#pragma unroll
+            for (int i = 0; i < UB; ++i) {
+                const int u = u0 + i * CTA_WG;
+                const int tc = u % TCH, kg = u / TCH;
+#pragma unroll
+                for (int r = 0; r < VEC; ++r) {
+                    const int k = min(kg * VEC + r, K - 1);
+                    v[i][r] = *reinterpret_cast<const vin*>(Xt + (int64_t)k * pitch + tc * LV);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < UB; ++i) {
+                const int u = u0 + i * CTA_WG;
+                const int tc = u % TCH, kg = u / TCH;
+#pragma unroll
+                for (int c = 0; c < LV; ++c) {
+                    typename T::frag f;
+#pragma unroll
+                    for (int r = 0; r < VEC; ++r)
+                        f[r] = kg * VEC + r < K ? cvt<Tc>(v[i][r][c]) : cvt<Tc>(0.f);
+                    *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
+                }
+            }
+        }
+        for (int u = nfull + threadIdx.x; u < nunits; u += CTA_WG) {
+            const int tc = u % TCH, kg = u / TCH;
+            vin v[VEC];
+#pragma unroll
+            for (int r = 0; r < VEC; ++r) {
+                const int k = min(kg * VEC + r, K - 1);
+                v[r] = *reinterpret_cast<const vin*>(Xt + (int64_t)k * pitch + tc * LV);
+            }
+#pragma unroll
+            for (int c = 0; c < LV; ++c) {
+                typename T::frag f;
+#pragma unroll
+                for (int r = 0; r < VEC; ++r) f[r] = kg * VEC + r < K ? cvt<Tc>(v[r][c]) : cvt<Tc>(0.f);
+                *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
+            }
+        }
+        return;
+    }
+    const bool vec_ok = (pitch % LV) == 0;
+    for (int u = threadIdx.x; u < nunits; u += CTA_WG) {
+        const int tc = u % TCH;
+        const int kg = u / TCH;
+        const int64_t t = t0 + (int64_t)tc * LV;
+        Tin v[VEC][LV];
+#pragma unroll
+        for (int r = 0; r < VEC; ++r) {
+            const int k = kg * VEC + r;
+            if (k < K && vec_ok && t + LV <= ncol) {
+                vin x = *reinterpret_cast<const vin*>(X + (int64_t)k * pitch + t);
+#pragma unroll
+                for (int c = 0; c < LV; ++c) v[r][c] = x[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < LV; ++c)
+                    v[r][c] = (k < K && t + c < ncol) ? X[(int64_t)k * pitch + t + c] : cvt<Tin>(0.f);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < LV; ++c) {
+            typename T::frag f;
+#pragma unroll
+            for (int r = 0; r < VEC; ++r) f[r] = cvt<Tc>(v[r][c]);
+            *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// acc[x][y] += Xs columns (cb + 16y ...) times M rows (jb + 16x ...) over kpad.
+// The M fragments of the next k step are loaded while the current one
+// multiplies (M is read from the cache hierarchy, not LDS, so its latency is
+// hidden by the MFMAs of the step before).
+template <typename Tc, int JT, int CT>
+__device__ __forceinline__ void mfma_cols(const Tc* Xs, int ldx, const Tc* __restrict__ M, int ldm,
+                                          int cb, int jb, int kpad,
+                                          typename MT<Tc>::acc (&acc)[JT][CT]) {
+    typedef MT<Tc> T;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, l16 = lane & 15;
+    const int nks = kpad / T::KSTEP;
+    const Tc* mrow[JT];
+#pragma unroll
+    for (int x = 0; x < JT; ++x) mrow[x] = M + (int64_t)(jb + x * 16 + l16) * ldm + T::VEC * g;
+    typename T::frag mb[JT];
+#pragma unroll
+    for (int x = 0; x < JT; ++x) mb[x] = *reinterpret_cast<const typename T::frag*>(mrow[x]);
+    for (int ks = 0; ks < nks; ++ks) {
+        const int k0 = ks * T::KSTEP + T::VEC * g;
+        const int kn = (ks + 1 < nks ? ks + 1 : ks) * T::KSTEP;
+        typename T::frag xa[CT], mn[JT];
+#pragma unroll
+        for (int x = 0; x < JT; ++x) mn[x] = *reinterpret_cast<const typename T::frag*>(mrow[x] + kn);
+#pragma unroll
+        for (int y = 0; y < CT; ++y)
+            xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (cb + y * 16 + l16) * ldx + k0);
+#pragma unroll
+        for (int x = 0; x < JT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
+#pragma unroll
+        for (int x = 0; x < JT; ++x) mb[x] = mn[x];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Strided pass.  Waves are arranged WJ x WC; a wave owns JT j-tiles and CT
 // column tiles of 16.  TN = 16*CT*WC columns, JPAD = 16*JT*WJ output rows.
 template <typename Tin, typename Tout, typename Tc, int JT, int WJ, int CT, bool EPI>
@@ -125,36 +258,7 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int64_t tile,
 
     // ---- stage X[b, 0:kpad, t0:t0+TN] into LDS as Xs[t][k] ----
     const bool vec_ok = (a.trail % LV) == 0;
-    constexpr int TCH = TN / LV;              // 16-byte chunks per row
-    const int nunits = (a.kpad / VEC) * TCH;  // (VEC rows) x (LV columns) units
-    for (int u = threadIdx.x; u < nunits; u += CTA_WG) {
-        const int tc = u % TCH;
-        const int kg = u / TCH;
-        const int64_t t = t0 + (int64_t)tc * LV;
-        Tin v[VEC][LV];
-#pragma unroll
-        for (int r = 0; r < VEC; ++r) {
-            const int k = kg * VEC + r;
-            if (k < a.K && vec_ok && t + LV <= a.trail) {
-                typedef Tin __attribute__((ext_vector_type(LV))) vin;
-                vin x = *reinterpret_cast<const vin*>(X + (int64_t)k * a.trail + t);
-#pragma unroll
-                for (int c = 0; c < LV; ++c) v[r][c] = x[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < LV; ++c)
-                    v[r][c] = (k < a.K && t + c < a.trail) ? X[(int64_t)k * a.trail + t + c]
-                                                          : cvt<Tin>(0.f);
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < LV; ++c) {
-            typename T::frag f;
-#pragma unroll
-            for (int r = 0; r < VEC; ++r) f[r] = cvt<Tc>(v[r][c]);
-            *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
-        }
-    }
+    stage_cols<Tin, Tc, TN>(X, a.trail, a.K, a.kpad, t0, a.trail, Xs, ldx);
     __syncthreads();
 
     // ---- MFMA: D[c][j] = sum_k Xs[c][k] * M[j][k] ----
@@ -167,21 +271,7 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int64_t tile,
     for (int x = 0; x < JT; ++x)
 #pragma unroll
         for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
-    const int nks = a.kpad / T::KSTEP;
-    for (int ks = 0; ks < nks; ++ks) {
-        const int k0 = ks * T::KSTEP + VEC * g;
-        typename T::frag xa[CT], mb[JT];
-#pragma unroll
-        for (int y = 0; y < CT; ++y)
-            xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (cb + y * 16 + l16) * ldx + k0);
-#pragma unroll
-        for (int x = 0; x < JT; ++x)
-            mb[x] = *reinterpret_cast<const typename T::frag*>(M + (int64_t)(jb + x * 16 + l16) * a.ldm + k0);
-#pragma unroll
-        for (int x = 0; x < JT; ++x)
-#pragma unroll
-            for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
-    }
+    mfma_cols<Tc, JT, CT>(Xs, ldx, M, a.ldm, cb, jb, a.kpad, acc);
 
     // ---- epilogue / store: lane owns rows j, columns c = arow(lane, r) ----
 #pragma unroll
@@ -300,38 +390,7 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
     const Tc* __restrict__ M = reinterpret_cast<const Tc*>(a.M);
 
     // ---- stage the X tile (transposed, Tc) ----
-    const bool vec_ok = (trail % LV) == 0;
-    {
-        constexpr int TCH = TN / LV;
-        const int nunits = (a.kpad / VEC) * TCH;
-        for (int u = threadIdx.x; u < nunits; u += CTA_WG) {
-            const int tc = u % TCH;
-            const int kg = u / TCH;
-            const int t = t0 + tc * LV;
-            Tin v[VEC][LV];
-#pragma unroll
-            for (int r = 0; r < VEC; ++r) {
-                const int k = kg * VEC + r;
-                if (k < K && vec_ok && t + LV <= trail) {
-                    typedef Tin __attribute__((ext_vector_type(LV))) vin;
-                    vin x = *reinterpret_cast<const vin*>(X + (int64_t)k * trail + t);
-#pragma unroll
-                    for (int c = 0; c < LV; ++c) v[r][c] = x[c];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < LV; ++c)
-                        v[r][c] = (k < K && t + c < trail) ? X[(int64_t)k * trail + t + c] : cvt<Tin>(0.f);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < LV; ++c) {
-                typename T::frag f;
-#pragma unroll
-                for (int r = 0; r < VEC; ++r) f[r] = cvt<Tc>(v[r][c]);
-                *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
-            }
-        }
-    }
+    stage_cols<Tin, Tc, TN>(X, trail, K, a.kpad, t0, trail, Xs, ldx);
     // ---- stage the P window and the band rows ----
     const bool pvec = (trail % E) == 0;
     {
@@ -366,22 +425,7 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
         for (int x = 0; x < JT; ++x)
 #pragma unroll
             for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
-        const int nks = a.kpad / T::KSTEP;
-        for (int ks = 0; ks < nks; ++ks) {
-            const int k0 = ks * T::KSTEP + VEC * g;
-            typename T::frag xa[CT], mb[JT];
-#pragma unroll
-            for (int y = 0; y < CT; ++y)
-                xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (cb + y * 16 + l16) * ldx + k0);
-#pragma unroll
-            for (int x = 0; x < JT; ++x)
-                mb[x] = *reinterpret_cast<const typename T::frag*>(
-                    M + (int64_t)(jb + x * 16 + l16) * a.ldm + k0);
-#pragma unroll
-            for (int x = 0; x < JT; ++x)
-#pragma unroll
-                for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
-        }
+        mfma_cols<Tc, JT, CT>(Xs, ldx, M, a.ldm, cb, jb, a.kpad, acc);
         __syncthreads();  // Xs is dead; its space becomes Qs
 #pragma unroll
         for (int x = 0; x < JT; ++x) {
@@ -801,36 +845,7 @@ __device__ __forceinline__ void normal_last_jtile(const StridedArgs& a, int64_t 
     const int iF = NF ? (int)((t0 / gm.sF) % gm.nF) : 0;
 
     // ---- stage the X tile (all K rows, transposed, Tc) ----
-    {
-        constexpr int TCH = TN / LV;
-        const int nunits = (a.kpad / VEC) * TCH;
-        for (int u = threadIdx.x; u < nunits; u += CTA_WG) {
-            const int tc = u % TCH;
-            const int kg = u / TCH;
-            const int t = t0 + tc * LV;
-            Tin v[VEC][LV];
-#pragma unroll
-            for (int r = 0; r < VEC; ++r) {
-                const int k = kg * VEC + r;
-                typedef Tin __attribute__((ext_vector_type(LV))) vin;
-                if (k < K) {
-                    const vin x = *reinterpret_cast<const vin*>(X + (int64_t)k * trail + t);
-#pragma unroll
-                    for (int c = 0; c < LV; ++c) v[r][c] = x[c];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < LV; ++c) v[r][c] = cvt<Tin>(0.f);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < LV; ++c) {
-                typename T::frag f;
-#pragma unroll
-                for (int r = 0; r < VEC; ++r) f[r] = cvt<Tc>(v[r][c]);
-                *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
-            }
-        }
-    }
+    stage_cols<Tin, Tc, TN>(X, trail, K, a.kpad, t0, trail, Xs, ldx);
     // ---- stage the P window (rows j0-2 .. j0+JB+1, zero outside the tensor) ----
     {
         const int cpr = LDW / 4;
@@ -998,11 +1013,42 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
         typename T::acc acc[J2T];
 #pragma unroll
         for (int x = 0; x < J2T; ++x) acc[x] = T::zero();
+        if constexpr (!FUSE_P) {
+            // X and M2 fragments of the next k step are loaded while the
+            // current one multiplies (j2 tiles past nj2t read the last valid
+            // one and are not used)
+            const Tin* __restrict__ xrow = X + (int64_t)i1 * a.K2;
+            auto xload = [&](int ks) {
+                const int k2 = ks * T::KSTEP + VEC * g;
+                const int nv = (i1 < a.K1) ? max(0, min(VEC, a.K2 - k2)) : 0;
+                return nv > 0 ? load_frag<Tc>(xrow + k2, nv, aligned2) : T::zfrag();
+            };
+            typename T::frag xf = xload(0), mf[J2T];
+#pragma unroll
+            for (int x = 0; x < J2T; ++x)
+                mf[x] = *reinterpret_cast<const typename T::frag*>(
+                    M2 + (int64_t)(min(x, nj2t - 1) * 16 + l16) * a.ldm2 + VEC * g);
+            for (int ks = 0; ks < nks2; ++ks) {
+                const int kn = ks + 1 < nks2 ? ks + 1 : ks;
+                const typename T::frag xn = xload(kn);
+                typename T::frag mn[J2T];
+#pragma unroll
+                for (int x = 0; x < J2T; ++x)
+                    mn[x] = *reinterpret_cast<const typename T::frag*>(
+                        M2 + (int64_t)(min(x, nj2t - 1) * 16 + l16) * a.ldm2 + kn * T::KSTEP + VEC * g);
+#pragma unroll
+                for (int x = 0; x < J2T; ++x)
+                    if (x < nj2t) acc[x] = T::mma(xf, mf[x], acc[x]);
+                xf = xn;
+#pragma unroll
+                for (int x = 0; x < J2T; ++x) mf[x] = mn[x];
+            }
+        } else
         for (int ks = 0; ks < nks2; ++ks) {
             const int k2 = ks * T::KSTEP + VEC * g;
             const int nv = (i1 < a.K1) ? max(0, min(VEC, a.K2 - k2)) : 0;
             typename T::frag xf = T::zfrag();
-            if constexpr (FUSE_P) {
+            {
                 // x += alpha p (previous step, optional), then p = r + beta * p on
                 // the fly; the new p is written back once
                 Tin* __restrict__ Pv = reinterpret_cast<Tin*>(a.Pvec) + off0;
@@ -1036,8 +1082,6 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
                         }
                     }
                 }
-            } else {
-                if (nv > 0) xf = load_frag<Tc>(X + (int64_t)i1 * a.K2 + k2, nv, aligned2);
             }
 #pragma unroll
             for (int x = 0; x < J2T; ++x) {
@@ -1070,13 +1114,16 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
         const int x2 = sb % nj2t, x1 = sb / nj2t;
         const Tc* Zb = Zt + bl * zsz;
         typename T::acc acc = T::zero();
+        // the M1 fragment of the next k step is loaded during the current MFMA
+        const Tc* __restrict__ m1row = M1 + (int64_t)(x1 * 16 + l16) * a.ldm1 + VEC * g;
+        const Tc* zrow = Zb + (x2 * 16 + l16) * ldz + VEC * g;
+        typename T::frag mf = *reinterpret_cast<const typename T::frag*>(m1row);
         for (int ks = 0; ks < nks1; ++ks) {
-            const int k1 = ks * T::KSTEP + VEC * g;
-            const typename T::frag zf =
-                *reinterpret_cast<const typename T::frag*>(Zb + (x2 * 16 + l16) * ldz + k1);
-            const typename T::frag mf = *reinterpret_cast<const typename T::frag*>(
-                M1 + (int64_t)(x1 * 16 + l16) * a.ldm1 + k1);
+            const int kn = (ks + 1 < nks1 ? ks + 1 : ks) * T::KSTEP;
+            const typename T::frag mn = *reinterpret_cast<const typename T::frag*>(m1row + kn);
+            const typename T::frag zf = *reinterpret_cast<const typename T::frag*>(zrow + ks * T::KSTEP);
             acc = T::mma(zf, mf, acc);
+            mf = mn;
         }
         const int j1 = x1 * 16 + l16;
         if (j1 < a.J1) {
