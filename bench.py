@@ -429,6 +429,22 @@ def main():
                "converged": all(i["status"] == 0 and i["rel_res_true"] <= 1e-8 for i in pinfos),
                "speedup_vs_plain_cg": round(elapsed / pel, 3)}
         X_pre = X.clone()
+        # one more step under the HIP-event tracer: per-kernel time per solve
+        cta.cta_prof_reset()
+        cta.cta_prof_enable(True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        pstep()
+        torch.cuda.synchronize()
+        ptr_ms = (time.perf_counter() - t2) * 1e3
+        cta.cta_prof_enable(False)
+        pprof = cta.cta_prof_read()
+        cta.cta_prof_reset()
+        pre["traced_ms_per_step"] = round(ptr_ms, 2)
+        pre["kernels_per_solve"] = {
+            k: {"count": v["count"], "avg_ms": round(v["total_ms"] / v["count"], 4),
+                "ms": round(v["total_ms"], 3), "share": round(v["total_ms"] / ptr_ms, 4)}
+            for k, v in sorted(pprof.items(), key=lambda kv: -kv[1]["total_ms"])[:14]}
 
     iters = sum(i["iters"] for i in infos)
     refine = sum(i["refine_steps"] for i in infos)

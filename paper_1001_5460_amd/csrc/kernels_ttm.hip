@@ -50,10 +50,54 @@ static hipError_t go_strided(StridedArgs a, const int* done, hipStream_t s) {
     return hipGetLastError();
 }
 
-// variant 0: 64-column tiles; variant 1: 128-column tiles (twice the columns per wave)
+template <typename Tin, typename Tout, typename Tc, int JT, int WJ, int CT>
+__global__ __launch_bounds__(CTA_WG) void k_strided_flat(StridedArgs a, const int* done) {
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Tc* Xs = reinterpret_cast<Tc*>(smem);
+    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
+        strided_flat_tile<Tin, Tout, Tc, JT, WJ, CT>(a, tile, Xs);
+}
+
+template <typename Tin, typename Tout, typename Tc, int JT, int WJ, int CT>
+static hipError_t go_strided_flat(StridedArgs a, const int* done, hipStream_t s) {
+    constexpr int TN = 16 * CT * (CTA_WAVES / WJ);
+    a.ntiles = (a.lead * a.trail + TN - 1) / TN;
+    fastdiv_init((uint32_t)a.trail, &a.tmul, &a.tshift);
+    const size_t lds = (size_t)TN * (a.kpad + 16 / sizeof(Tc)) * sizeof(Tc);
+    auto kern = k_strided_flat<Tin, Tout, Tc, JT, WJ, CT>;
+    hipError_t e = ensure_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    kern<<<grid_for(a.ntiles, 65536), CTA_WG, lds, s>>>(a, done);
+    return hipGetLastError();
+}
+
+// Flattened columns pay off when the per-b tiles of 64 columns would leave
+// more than an eighth of the MFMA columns empty (short or ragged trail).
+template <typename Tin, typename Tc>
+static bool use_flat(const StridedArgs& a) {
+    constexpr int LV = 16 / sizeof(Tin);
+    if (a.lead < 2 || a.trail % LV != 0 || (MT<Tc>::CONSEC && a.trail % 4 != 0)) return false;
+    if (a.lead * a.trail >= ((int64_t)1 << 31)) return false;
+    const int64_t padded = (a.trail + 63) / 64 * 64;
+    return (padded - a.trail) * 8 > padded;
+}
+
+// variant 0: 64-column tiles; variant 1: 128-column tiles (twice the columns
+// per wave); either takes flattened 64-column tiles when use_flat says so
 template <typename Tin, typename Tout, typename Tc>
 static hipError_t strided_T(StridedArgs a, int variant, const int* done, hipStream_t s) {
     const int jt = (a.J + 15) / 16;
+    if (use_flat<Tin, Tc>(a)) {
+        if (jt <= 1) return go_strided_flat<Tin, Tout, Tc, 1, 1, 1>(a, done, s);
+        if (jt <= 2) return go_strided_flat<Tin, Tout, Tc, 1, 2, 2>(a, done, s);
+        if (jt <= 4) return go_strided_flat<Tin, Tout, Tc, 1, 4, 4>(a, done, s);
+        if (jt <= 6) return go_strided_flat<Tin, Tout, Tc, 3, 2, 2>(a, done, s);
+        if (jt <= 8) return go_strided_flat<Tin, Tout, Tc, 2, 4, 4>(a, done, s);
+        if (jt <= 12) return go_strided_flat<Tin, Tout, Tc, 3, 4, 4>(a, done, s);
+        if (jt <= 16) return go_strided_flat<Tin, Tout, Tc, 4, 4, 4>(a, done, s);
+        return hipErrorInvalidValue;
+    }
     if (variant == 1) {
         if (jt <= 1) return go_strided<Tin, Tout, Tc, 1, 1, 2>(a, done, s);
         if (jt <= 2) return go_strided<Tin, Tout, Tc, 1, 2, 4>(a, done, s);

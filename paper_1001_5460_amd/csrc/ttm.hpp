@@ -62,6 +62,9 @@ struct StridedArgs {
     // mode are loaded by tiles that run at nearly the same time.
     int64_t plane;
     int nplane, pgroup;
+    // flattened-column pass (strided_flat_tile): division by trail
+    uint32_t tmul;
+    int tshift;
 };
 
 // First column of tile `tile` of the last pass (see StridedArgs::pgroup).
@@ -106,17 +109,23 @@ struct ContigArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Stage columns [t0, t0 + TN) of a row-major K x ncol slab X (row pitch
-// `pitch` elements) into LDS transposed, Xs[c * ldx + k] in Tc; rows K..kpad-1
-// and columns at or past ncol are zero.  A unit is VEC rows x LV columns (one
-// 16-byte load per row).  Interior tiles take a branch-free path: row and unit
-// indices are clamped so every address is valid, the loads of UB units are
-// issued before the first LDS write, and out-of-range values are replaced by
-// zero afterwards, so a thread keeps UB * VEC loads in flight instead of one
+// Stage TN columns of K rows into LDS transposed, Xs[c * ldx + k] in Tc, rows
+// K..kpad-1 zero.  A unit is VEC rows x LV columns (one 16-byte load per row);
+// col(tc) gives the address of row 0 of the LV columns tc*LV.. and whether
+// they exist (when not, the address must still be readable and the unit is
+// stored as zero).  Rows are `pitch` elements apart.  Row indices are clamped
+// so every load is valid, and the loads of UB units are issued before the
+// first LDS write, so a thread keeps UB * VEC loads in flight instead of one
 // (units past the last whole batch of UB * CTA_WG go one at a time).
-template <typename Tin, typename Tc, int TN>
-__device__ __forceinline__ void stage_cols(const Tin* __restrict__ X, int64_t pitch, int K,
-                                           int kpad, int64_t t0, int64_t ncol, Tc* Xs, int ldx) {
+template <typename Tin>
+struct ColPtr {
+    const Tin* p;
+    bool ok;
+};
+
+template <typename Tin, typename Tc, int TN, typename ColFn>
+__device__ __forceinline__ void stage_units(ColFn col, int64_t pitch, int K, int kpad, Tc* Xs,
+                                            int ldx) {
     typedef MT<Tc> T;
     constexpr int VEC = T::VEC;
     constexpr int LV = 16 / sizeof(Tin);
@@ -124,52 +133,65 @@ __device__ __forceinline__ void stage_cols(const Tin* __restrict__ X, int64_t pi
     constexpr int UB = 4;
     typedef Tin __attribute__((ext_vector_type(LV))) vin;
     const int nunits = (kpad / VEC) * TCH;
-    if ((pitch % LV) == 0 && t0 + TN <= ncol) {
-        const Tin* __restrict__ Xt = X + t0;
-        // whole batches: every unit valid, no branch between loads and stores
-        const int nfull = nunits / (CTA_WG * UB) * (CTA_WG * UB);
-        for (int u0 = threadIdx.x; u0 < nfull; u0 += CTA_WG * UB) {
-            vin v[UB][VEC];
+    auto store = [&](int u, const vin (&v)[VEC], bool ok) {
+        const int tc = u % TCH, kg = u / TCH;
 #pragma unroll
-            for (int i = 0; i < UB; ++i) {
-                const int u = u0 + i * CTA_WG;
-                const int tc = u % TCH, kg = u / TCH;
+        for (int c = 0; c < LV; ++c) {
+            typename T::frag f;
 #pragma unroll
-                for (int r = 0; r < VEC; ++r) {
-                    const int k = min(kg * VEC + r, K - 1);
-                    v[i][r] = *reinterpret_cast<const vin*>(Xt + (int64_t)k * pitch + tc * LV);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < UB; ++i) {
-                const int u = u0 + i * CTA_WG;
-                const int tc = u % TCH, kg = u / TCH;
-#pragma unroll
-                for (int c = 0; c < LV; ++c) {
-                    typename T::frag f;
-#pragma unroll
-                    for (int r = 0; r < VEC; ++r)
-                        f[r] = kg * VEC + r < K ? cvt<Tc>(v[i][r][c]) : cvt<Tc>(0.f);
-                    *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
-                }
-            }
+            for (int r = 0; r < VEC; ++r)
+                f[r] = ok && kg * VEC + r < K ? cvt<Tc>(v[r][c]) : cvt<Tc>(0.f);
+            *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
         }
-        for (int u = nfull + threadIdx.x; u < nunits; u += CTA_WG) {
+    };
+    const int nfull = nunits / (CTA_WG * UB) * (CTA_WG * UB);
+    for (int u0 = threadIdx.x; u0 < nfull; u0 += CTA_WG * UB) {
+        vin v[UB][VEC];
+        bool ok[UB];
+#pragma unroll
+        for (int i = 0; i < UB; ++i) {
+            const int u = u0 + i * CTA_WG;
             const int tc = u % TCH, kg = u / TCH;
-            vin v[VEC];
+            const auto cp = col(tc);
+            ok[i] = cp.ok;
 #pragma unroll
             for (int r = 0; r < VEC; ++r) {
                 const int k = min(kg * VEC + r, K - 1);
-                v[r] = *reinterpret_cast<const vin*>(Xt + (int64_t)k * pitch + tc * LV);
-            }
-#pragma unroll
-            for (int c = 0; c < LV; ++c) {
-                typename T::frag f;
-#pragma unroll
-                for (int r = 0; r < VEC; ++r) f[r] = kg * VEC + r < K ? cvt<Tc>(v[r][c]) : cvt<Tc>(0.f);
-                *reinterpret_cast<typename T::frag*>(Xs + (tc * LV + c) * ldx + kg * VEC) = f;
+                v[i][r] = *reinterpret_cast<const vin*>(cp.p + (int64_t)k * pitch);
             }
         }
+#pragma unroll
+        for (int i = 0; i < UB; ++i) store(u0 + i * CTA_WG, v[i], ok[i]);
+    }
+    for (int u = nfull + threadIdx.x; u < nunits; u += CTA_WG) {
+        const int tc = u % TCH, kg = u / TCH;
+        const auto cp = col(tc);
+        vin v[VEC];
+#pragma unroll
+        for (int r = 0; r < VEC; ++r) {
+            const int k = min(kg * VEC + r, K - 1);
+            v[r] = *reinterpret_cast<const vin*>(cp.p + (int64_t)k * pitch);
+        }
+        store(u, v, cp.ok);
+    }
+}
+
+// Stage columns [t0, t0 + TN) of a row-major K x ncol slab X (row pitch
+// `pitch` elements) into LDS transposed (see stage_units); columns at or past
+// ncol are zero.  Interior tiles take the batched path of stage_units.
+template <typename Tin, typename Tc, int TN>
+__device__ __forceinline__ void stage_cols(const Tin* __restrict__ X, int64_t pitch, int K,
+                                           int kpad, int64_t t0, int64_t ncol, Tc* Xs, int ldx) {
+    typedef MT<Tc> T;
+    constexpr int VEC = T::VEC;
+    constexpr int LV = 16 / sizeof(Tin);
+    constexpr int TCH = TN / LV;
+    typedef Tin __attribute__((ext_vector_type(LV))) vin;
+    const int nunits = (kpad / VEC) * TCH;
+    if ((pitch % LV) == 0 && t0 + TN <= ncol) {
+        const Tin* __restrict__ Xt = X + t0;
+        stage_units<Tin, Tc, TN>([&](int tc) { return ColPtr<Tin>{Xt + tc * LV, true}; }, pitch, K,
+                                 kpad, Xs, ldx);
         return;
     }
     const bool vec_ok = (pitch % LV) == 0;
@@ -328,6 +350,79 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int64_t tile,
                     const Tout qv = cvt<Tout>(acc[x][y][r]) + cvt<Tout>(st->lam) * s;
                     Y[base] = qv;
                     dot_acc += (double)pv * (double)qv;
+                }
+            }
+        }
+    }
+    __syncthreads();  // Xs is reused by the next tile
+}
+
+// ---------------------------------------------------------------------------
+// Strided pass over flattened columns: the lead * trail columns (b, t) are
+// numbered c = b * trail + t and tiled TN at a time across b, so a trail that
+// is short or not a multiple of TN wastes no MFMA columns.  Needs
+// trail % LV == 0 (a 16-byte unit never straddles two b), trail % 4 == 0 when
+// T::CONSEC (nor does a 4-column output run) and lead * trail < 2^31.
+template <typename Tin, typename Tout, typename Tc, int JT, int WJ, int CT>
+__device__ __forceinline__ void strided_flat_tile(const StridedArgs& a, int64_t tile, Tc* Xs) {
+    typedef MT<Tc> T;
+    constexpr int WC = CTA_WAVES / WJ;
+    constexpr int TN = 16 * CT * WC;
+    constexpr int LV = 16 / sizeof(Tin);
+    const int ldx = a.kpad + 16 / (int)sizeof(Tc);
+    const int trail = (int)a.trail;
+    const int ncol = (int)(a.lead * a.trail);
+    const int c0 = (int)tile * TN;
+    const int64_t bin = (int64_t)a.K * trail, bout = (int64_t)a.J * trail;
+    const Tin* __restrict__ X = reinterpret_cast<const Tin*>(a.X);
+    Tout* __restrict__ Y = reinterpret_cast<Tout*>(a.Y);
+    const Tc* __restrict__ M = reinterpret_cast<const Tc*>(a.M);
+
+    stage_units<Tin, Tc, TN>(
+        [&](int tc) {
+            const int c = c0 + tc * LV;
+            const bool ok = c < ncol;
+            const int cc = ok ? c : 0;
+            const int b = fast_div(cc, a.tmul, a.tshift);
+            return ColPtr<Tin>{X + b * bin + (cc - b * trail), ok};
+        },
+        trail, a.K, a.kpad, Xs, ldx);
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wj = wave % WJ, wc = wave / WJ;
+    const int cb = wc * CT * 16, jb = wj * JT * 16;
+    const int g = lane >> 4, l16 = lane & 15;
+    typename T::acc acc[JT][CT];
+#pragma unroll
+    for (int x = 0; x < JT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
+    mfma_cols<Tc, JT, CT>(Xs, ldx, M, a.ldm, cb, jb, a.kpad, acc);
+
+#pragma unroll
+    for (int x = 0; x < JT; ++x) {
+        const int j = jb + x * 16 + l16;
+        if (j >= a.J) continue;
+#pragma unroll
+        for (int y = 0; y < CT; ++y) {
+            const int cbase = c0 + cb + y * 16;
+            if constexpr (T::CONSEC) {
+                const int c = cbase + 4 * g;
+                if (c >= ncol) continue;
+                const int b = fast_div(c, a.tmul, a.tshift);
+                typedef Tout __attribute__((ext_vector_type(4))) vout;
+                vout o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = cvt<Tout>(acc[x][y][r]);
+                *reinterpret_cast<vout*>(Y + b * bout + (int64_t)j * trail + (c - b * trail)) = o;
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = cbase + T::arow(lane, r);
+                    if (c >= ncol) continue;
+                    const int b = fast_div(c, a.tmul, a.tshift);
+                    Y[b * bout + (int64_t)j * trail + (c - b * trail)] = cvt<Tout>(acc[x][y][r]);
                 }
             }
         }
@@ -1169,17 +1264,31 @@ __device__ __forceinline__ void contig_rows(const ContigArgs& a, int64_t rtile) 
 #pragma unroll
     for (int x = 0; x < JT; ++x) acc[x] = T::zero();
     const int nks = a.kpad / T::KSTEP;
-    for (int ks = 0; ks < nks; ++ks) {
+    // the X and M fragments of the next k step are loaded while the current
+    // one multiplies
+    auto xload = [&](int ks) {
         const int k = ks * T::KSTEP + VEC * g;
         const int nv = (row < a.rows) ? max(0, min(VEC, a.K - k)) : 0;
-        const typename T::frag xf =
-            (nv > 0) ? load_frag<Tc>(X + row * a.K + k, nv, (a.K % VEC) == 0) : T::zfrag();
+        return (nv > 0) ? load_frag<Tc>(X + row * a.K + k, nv, (a.K % VEC) == 0) : T::zfrag();
+    };
+    const Tc* mrow[JT];
 #pragma unroll
-        for (int x = 0; x < JT; ++x) {
-            const typename T::frag mf = *reinterpret_cast<const typename T::frag*>(
-                M + (int64_t)(a.j0 + x * 16 + l16) * a.ldm + k);
-            acc[x] = T::mma(mf, xf, acc[x]);
-        }
+    for (int x = 0; x < JT; ++x) mrow[x] = M + (int64_t)(a.j0 + x * 16 + l16) * a.ldm + VEC * g;
+    typename T::frag xf = xload(0), mf[JT];
+#pragma unroll
+    for (int x = 0; x < JT; ++x) mf[x] = *reinterpret_cast<const typename T::frag*>(mrow[x]);
+    for (int ks = 0; ks < nks; ++ks) {
+        const int kn = ks + 1 < nks ? ks + 1 : ks;
+        const typename T::frag xn = xload(kn);
+        typename T::frag mn[JT];
+#pragma unroll
+        for (int x = 0; x < JT; ++x)
+            mn[x] = *reinterpret_cast<const typename T::frag*>(mrow[x] + kn * T::KSTEP);
+#pragma unroll
+        for (int x = 0; x < JT; ++x) acc[x] = T::mma(mf[x], xf, acc[x]);
+        xf = xn;
+#pragma unroll
+        for (int x = 0; x < JT; ++x) mf[x] = mn[x];
     }
     if (row >= a.rows) return;
 #pragma unroll

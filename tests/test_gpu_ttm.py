@@ -28,6 +28,9 @@ SINGLE = [
     ((7, 96, 48), 0, 20),
     ((2, 3, 192, 8), 2, 128), # rectangular 192 -> 128
     ((300, 16), 1, 256),      # widest output
+    # short trails: 64-column tiles span several leading indices, last tile ragged
+    ((11, 29, 12), 1, 31),    # trail 12, 132 columns
+    ((13, 45, 40), 1, 50),    # trail 40, 520 columns
 ]
 
 
