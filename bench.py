@@ -57,6 +57,14 @@ def chain_flops_rect(in_ext, out_ext):
     return best
 
 
+def active_avg_ms(v):
+    """Average duration of a kernel's active launches (the tracer leaves out
+    the launches that exited at once on a converged solve's flag)."""
+    n = v.get("active_count") or v["count"]
+    t = v.get("active_ms") if v.get("active_count") else v["total_ms"]
+    return t / n
+
+
 def algorithmic(name, N, n):
     """(bytes, flops) one launch of a kernel class moves / does on this workload.
 
@@ -442,8 +450,9 @@ def main():
         cta.cta_prof_reset()
         pre["traced_ms_per_step"] = round(ptr_ms, 2)
         pre["kernels_per_solve"] = {
-            k: {"count": v["count"], "avg_ms": round(v["total_ms"] / v["count"], 4),
-                "ms": round(v["total_ms"], 3), "share": round(v["total_ms"] / ptr_ms, 4)}
+            k: {"count": v["count"], "active": v.get("active_count", v["count"]),
+                "avg_ms": round(active_avg_ms(v), 4), "ms": round(v["total_ms"], 3),
+                "share": round(v["total_ms"] / ptr_ms, 4)}
             for k, v in sorted(pprof.items(), key=lambda kv: -kv[1]["total_ms"])[:14]}
 
     iters = sum(i["iters"] for i in infos)
@@ -459,7 +468,7 @@ def main():
 
     # dominant kernel: largest total time in the timed region
     dom = max(prof, key=lambda k: prof[k]["total_ms"])
-    avg_s = prof[dom]["total_ms"] / prof[dom]["count"] / 1e3
+    avg_s = active_avg_ms(prof[dom]) / 1e3
     alg = algorithmic(dom, N, n)
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -478,14 +487,14 @@ def main():
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": alg[0], "avg_launch_ms": round(avg_s * 1e3, 4),
-                "launches": prof[dom]["count"]}
+                "launches": prof[dom]["count"], "active_launches": prof[dom].get("active_count")}
     elif alg is not None:
         achieved = alg[1] / avg_s / 1e12
         roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
                 "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic,
                 "algorithmic_flops_per_launch": alg[1], "avg_launch_ms": round(avg_s * 1e3, 4),
-                "launches": prof[dom]["count"]}
+                "launches": prof[dom]["count"], "active_launches": prof[dom].get("active_count")}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": None, "traffic": traffic}
@@ -493,8 +502,8 @@ def main():
     kernels = {}
     for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
         a = algorithmic(k, N, n)
-        avg = v["total_ms"] / v["count"]
-        e = {"count": v["count"], "avg_ms": round(avg, 4),
+        avg = active_avg_ms(v)
+        e = {"count": v["count"], "active": v.get("active_count", v["count"]), "avg_ms": round(avg, 4),
              "share": round(v["total_ms"] / (traced_elapsed * 1e3), 4)}
         if a and a[0]:
             e["GB/s"] = round(a[0] / (avg / 1e3) / 1e9, 1)

@@ -219,7 +219,10 @@ typedef struct {
     int fallback_zero;  /* 1: use zero if the start is worse than zero */
     double inner_rtol;  /* refinement: inner relative tolerance (e.g. 1e-2) */
     int max_refine;     /* refinement: outer steps */
-    int check_every;    /* host reads the convergence flag every this many iterations */
+    int check_every;    /* host reads the convergence flag every this many iterations
+                           (reliable updates: the first read of a group after as many
+                           iterations as the previous group took, then every
+                           max(1, check_every / 4)) */
     int precond;        /* 1: preconditioned CG with the operator's tensor-inverse
                            preconditioner (cta_op_set_preconditioner); the
                            iteration uses z = M^-1 r for the search direction and
@@ -332,9 +335,12 @@ cta_status cta_ws_params(cta_ws w, void* host_buf, size_t bytes, int set, void* 
  * bracketed by two HIP events recorded on the launch's stream (so the timing
  * is of the kernel as it ran inside the caller's work).  cta_prof_read
  * synchronises the recorded events and writes a JSON object
- * {"<kernel>": {"count", "total_ms", "min_ms", "max_ms"}, ...} into host_buf
- * (NUL terminated, truncated to bytes; the full length is returned in
- * *needed).  cta_prof_reset drops the records.  Process-wide; not meant for
+ * {"<kernel>": {"count", "total_ms", "min_ms", "max_ms", "active_count",
+ * "active_ms"}, ...} into host_buf (NUL terminated, truncated to bytes; the
+ * full length is returned in *needed).  The active figures cover the
+ * launches that ran at least a tenth of the kernel's 90th-percentile
+ * duration: the iterations a solver enqueues past convergence exit at once on
+ * the device-side converged flag, and they are left out there.  cta_prof_reset drops the records.  Process-wide; not meant for
  * concurrent use from several threads.
  * ---------------------------------------------------------------------- */
 cta_status cta_prof_enable(int on);

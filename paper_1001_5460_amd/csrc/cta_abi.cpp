@@ -687,6 +687,13 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
             const bool f32_ok = tail_fits(DT_F32, (int)op->n[N - 2], (int)op->n[N - 1]);
             CTA_HIP(launch_fill_zero(op->vx, (size_t)n * 4, s));
             CTA_HIP(launch_fill_zero(op->vp, (size_t)n * 4, s));
+            // Every group cuts the residual by the same factor eta, so groups take
+            // similar iteration counts: the first check of a group comes after as
+            // many iterations as the previous group took, later ones every
+            // check/4.  Iterations launched past convergence exit at once, but
+            // each still costs a dispatch.
+            int first_chunk = check;
+            const int later_chunk = std::max(1, check / 4);
             while (true) {
                 if (!std::isfinite(rr)) {
                     done = DONE_BREAKDOWN;
@@ -707,8 +714,8 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
                     CTA_TRY(apply_precond(op, op->vr, op->vaux, CTA_PREC_BF16, POST_DOT, &op->scal->dot2, false, s));
                 CTA_HIP(launch_cg_group(op->scal, thr, opts->max_iter, steps > 0 ? 1 : 0, s, pc ? 1 : 0));
                 int gdone = DONE_RUNNING;
-                for (;;) {
-                    for (int c = 0; c < check; ++c) {
+                for (int chunk = first_chunk;; chunk = later_chunk) {
+                    for (int c = 0; c < chunk; ++c) {
                         CTA_TRY(apply_normal(op, nullptr, op->vq, CTA_PREC_BF16, POST_ALPHA, nullptr, true, s,
                                              op->vx, pc ? op->vaux : nullptr));
                         CTA_HIP(launch_cg_update(DT_F32, nullptr, op->vr, op->vp, op->vq, n, op->partials,
@@ -722,6 +729,7 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
                 }
                 CTA_HIP(launch_x_flush(DT_F32, op->vx, op->vp, n, op->scal, s));
                 total += op->hscal->iters;
+                first_chunk = std::max(1, std::min(op->hscal->iters, 4 * check));
                 if (gdone == DONE_BREAKDOWN && op->hscal->iters == 0) {
                     done = DONE_BREAKDOWN;
                     break;

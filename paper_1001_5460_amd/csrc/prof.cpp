@@ -77,28 +77,35 @@ extern "C" cta_status cta_prof_reset(void) {
 
 extern "C" cta_status cta_prof_read(char* host_buf, size_t bytes, size_t* needed) {
     std::lock_guard<std::mutex> lk(g_mu);
-    struct Agg {
-        long count = 0;
-        double total_ms = 0, min_ms = 1e300, max_ms = 0;
-    };
-    std::map<std::string, Agg> agg;
+    std::map<std::string, std::vector<double>> dur;
     for (Rec& r : g_recs) {
         if (hipEventSynchronize(r.b) != hipSuccess) return fail(CTA_ERR_HIP, "event synchronize failed");
         float ms = 0;
         if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(CTA_ERR_HIP, "event timing failed");
-        Agg& g = agg[r.name];
-        g.count += 1;
-        g.total_ms += ms;
-        g.min_ms = std::min(g.min_ms, (double)ms);
-        g.max_ms = std::max(g.max_ms, (double)ms);
+        dur[r.name].push_back(ms);
     }
     std::string out = "{";
     bool first = true;
-    for (auto& kv : agg) {
-        char buf[256];
-        snprintf(buf, sizeof buf, "%s\"%s\": {\"count\": %ld, \"total_ms\": %.6f, \"min_ms\": %.6f, \"max_ms\": %.6f}",
-                 first ? "" : ", ", kv.first.c_str(), kv.second.count, kv.second.total_ms,
-                 kv.second.min_ms, kv.second.max_ms);
+    for (auto& kv : dur) {
+        std::vector<double> d = kv.second;
+        std::sort(d.begin(), d.end());
+        double total = 0;
+        for (double v : d) total += v;
+        // active launches: at least a tenth of the 90th-percentile duration
+        // (launches gated by a converged solve's flag exit at once)
+        const double cut = 0.1 * d[(d.size() - 1) * 9 / 10];
+        long nact = 0;
+        double tact = 0;
+        for (double v : d)
+            if (v >= cut) {
+                ++nact;
+                tact += v;
+            }
+        char buf[320];
+        snprintf(buf, sizeof buf,
+                 "%s\"%s\": {\"count\": %ld, \"total_ms\": %.6f, \"min_ms\": %.6f, \"max_ms\": %.6f, "
+                 "\"active_count\": %ld, \"active_ms\": %.6f}",
+                 first ? "" : ", ", kv.first.c_str(), (long)d.size(), total, d.front(), d.back(), nact, tact);
         out += buf;
         first = false;
     }

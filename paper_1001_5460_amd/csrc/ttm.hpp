@@ -767,20 +767,7 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
             for (int x = 0; x < JT; ++x)
 #pragma unroll
                 for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
-            for (int ks = 0; ks < KPAD / T::KSTEP; ++ks) {
-                const int k0 = ks * T::KSTEP + VEC * g;
-                typename T::frag xa[CT], mb[JT];
-#pragma unroll
-                for (int y = 0; y < CT; ++y)
-                    xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (y * 16 + l16) * ldx + k0);
-#pragma unroll
-                for (int x = 0; x < JT; ++x)
-                    mb[x] = *reinterpret_cast<const typename T::frag*>(M + (int64_t)(jb + x * 16 + l16) * a.ldm + k0);
-#pragma unroll
-                for (int x = 0; x < JT; ++x)
-#pragma unroll
-                    for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
-            }
+            mfma_cols<bf16, JT, CT>(Xs, ldx, M, a.ldm, 0, jb, KPAD, acc);
             __syncthreads();  // Xs is dead; its space becomes Qs
 #pragma unroll
             for (int x = 0; x < JT; ++x) {
@@ -1100,6 +1087,52 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
     const bool aligned2 = (a.K2 % VEC) == 0;
 
     // ---- step 1: Zt[b][j2][i1] = sum_k2 X_b[i1][k2] M2[j2][k2] ----
+    if (!FUSE_P && nks2 == 1) {
+        // one k step: the M2 fragments are the same for every tile, and a wave
+        // loads the X fragments of TB tiles before the first MFMA, so TB loads
+        // are in flight together (tiles past the end load the last tile again
+        // and store nothing)
+        constexpr int TB = 4;
+        const int ntile = nb * ni1t;
+        typename T::frag mf[J2T];
+#pragma unroll
+        for (int x = 0; x < J2T; ++x)
+            mf[x] = *reinterpret_cast<const typename T::frag*>(
+                M2 + (int64_t)(min(x, nj2t - 1) * 16 + l16) * a.ldm2 + VEC * g);
+        const int k2 = VEC * g;
+        for (int it0 = wave; it0 < ntile; it0 += CTA_WAVES * TB) {
+            typename T::frag xf[TB];
+#pragma unroll
+            for (int i = 0; i < TB; ++i) {
+                const int it = min(it0 + i * CTA_WAVES, ntile - 1);
+                const int bl = it / ni1t, ti = it - bl * ni1t;
+                const int i1 = ti * 16 + l16;
+                const Tin* __restrict__ X = reinterpret_cast<const Tin*>(a.X) + (blk0 + bl) * bin;
+                const int nv = (i1 < a.K1) ? max(0, min(VEC, a.K2 - k2)) : 0;
+                xf[i] = nv > 0 ? load_frag<Tc>(X + (int64_t)i1 * a.K2 + k2, nv, aligned2) : T::zfrag();
+            }
+#pragma unroll
+            for (int i = 0; i < TB; ++i) {
+                const int it = it0 + i * CTA_WAVES;
+                typename T::acc acc[J2T];
+#pragma unroll
+                for (int x = 0; x < J2T; ++x)
+                    acc[x] = x < nj2t ? T::mma(xf[i], mf[x], T::zero()) : T::zero();
+                if (it >= ntile) continue;
+                const int bl = it / ni1t, ti = it - bl * ni1t;
+                Tc* Zb = Zt + bl * zsz;
+#pragma unroll
+                for (int x = 0; x < J2T; ++x) {
+                    if (x < nj2t) {
+                        const int j2 = x * 16 + l16;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            Zb[j2 * ldz + ti * 16 + T::arow(lane, r)] = cvt<Tc>(acc[x][r]);
+                    }
+                }
+            }
+        }
+    } else
     for (int it = wave; it < nb * ni1t; it += CTA_WAVES) {
         const int bl = it / ni1t, ti = it - bl * ni1t;
         const int64_t off0 = (blk0 + bl) * bin;
