@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 # copy-kernel calibration of the rocprofv3 FETCH_SIZE / WRITE_SIZE counters and the
 # traffic of the dominant kernel, both from profiles/ (None until measured)
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_normal_last_bf16_128x128x96x24.json")
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_headline_kernels_128x128x96x24.json")
 # trained warm-start network of the 64x64x64x16 blob workload
 WS_CKPT = os.path.join(HERE, "paper_1001_5460_amd", "weights", "ws_64x64x64x16.npz")
 
@@ -55,6 +55,18 @@ def chain_flops_rect(in_ext, out_ext):
             cur[k] = out_ext[k]
         best = f if best is None else min(best, f)
     return best
+
+
+def kernel_sources_digest():
+    """SHA-256 (first 16 hex digits) of the kernel sources, in name order."""
+    import hashlib
+    csrc = os.path.join(HERE, "paper_1001_5460_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def active_avg_ms(v):
@@ -475,11 +487,13 @@ def main():
         try:
             with open(TRAFFIC_FILE) as f:
                 tj = json.load(f)
-            # only for the same kernel and the same pass variants as this run
+            # only for the same pass variants as this run, and only while the
+            # kernel sources are the ones the counters were taken with
             tv = tuning.get("bf16", {})
             same = all(tj.get("tuning", {}).get(k) == tv.get(k) for k in ("tail", "middle", "last"))
-            if tj.get("kernel") == dom and same:
-                traffic = tj.get("traffic_bytes_per_launch")
+            ent = tj.get("kernels", {}).get(dom)
+            if same and ent is not None and ent.get("sources") == kernel_sources_digest():
+                traffic = ent.get("traffic_bytes_per_launch")
         except Exception:
             traffic = None
     if alg is not None and alg[0] > 0 and not dom.endswith(".f64"):

@@ -182,7 +182,8 @@ static hipError_t go_last(StridedArgs a, const StencilArgs<Tvec>& st, int* grid_
 
 // Pipelined persistent last pass (normal_last_pipe): BF16 chain, FP32 vectors,
 // 96 < K <= 128.
-__global__ __launch_bounds__(CTA_WG) void k_normal_last_pipe(StridedArgs a, StencilArgs<float> st,
+// three workgroups per CU (the LDS budget) need at most 168 registers per lane
+__global__ __launch_bounds__(CTA_WG) __attribute__((amdgpu_waves_per_eu(3))) void k_normal_last_pipe(StridedArgs a, StencilArgs<float> st,
                                                              const int* done) {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];

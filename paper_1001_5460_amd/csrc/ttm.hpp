@@ -564,6 +564,27 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
             vt reg;
 #pragma unroll
             for (int e = 0; e < E; ++e) reg[e] = Tv(0);
+            // summation order (kept by every last-pass variant): the middle modes,
+            // then mode 1, then mode N
+            const Tv* __restrict__ pb = P + base;
+            for (int k = 1; k < N - 1; ++k) {
+                const Tv* __restrict__ rb = st.rband[k];
+                if (!rb) continue;
+                const int sk = (int)st.stride[k], nk = (int)st.ext[k];
+                const int u = fast_div(t, st.smul[k], st.sshift[k]);
+                const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
+                const Tv* br = rb + ik * 5;
+                vt nbv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
+                    const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
+                    nbv[q] = *reinterpret_cast<const vt*>(pb + dd * sk);
+                }
+                reg += br[2] * pc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) reg += br[q < 2 ? q : q + 1] * nbv[q];
+            }
             if (has1) {
 #pragma unroll
                 for (int d = -2; d <= 2; ++d) {
@@ -588,25 +609,6 @@ __device__ __forceinline__ void normal_last_tile(const StridedArgs& a, int64_t t
 #pragma unroll
                     for (int d = -2; d <= 2; ++d) reg[e] += bN[d + 2] * w[E + e + d];
                 }
-            }
-            const Tv* __restrict__ pb = P + base;
-            for (int k = 1; k < N - 1; ++k) {
-                const Tv* __restrict__ rb = st.rband[k];
-                if (!rb) continue;
-                const int sk = (int)st.stride[k], nk = (int)st.ext[k];
-                const int u = fast_div(t, st.smul[k], st.sshift[k]);
-                const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
-                const Tv* br = rb + ik * 5;
-                vt nbv[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
-                    const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
-                    nbv[q] = *reinterpret_cast<const vt*>(pb + dd * sk);
-                }
-                reg += br[2] * pc;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) reg += br[q < 2 ? q : q + 1] * nbv[q];
             }
             const vt qv = s + lam * reg;
             *reinterpret_cast<vt*>(Q + base) = qv;
@@ -752,11 +754,54 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
     PipeRegs r;
     if (first < a.ntiles) pipe_load<KPAD>(a, P, (int)last_tile_col<TN>(a, first), K, r);
     const Tv lam = (Tv)st.lam;
+    // Order of the memory traffic inside one tile.  The vector-memory counter
+    // retires loads in issue order, so a load waits for every load issued
+    // before it.  The middle-mode taps (gathered from memory) therefore come
+    // first, then the MFMA with its G_1 fragments, and only then the prefetch
+    // of the next tile, which lands while the epilogue runs on LDS alone.
+    constexpr int GPR = TN / E;                 // items per row
+    constexpr int IPT = KPAD * GPR / CTA_WG;    // items per thread (rows <= KPAD)
+    const int nitem = a.J * GPR;
     for (int64_t tile = first; tile < a.ntiles; tile += step) {
         const int t0 = (int)last_tile_col<TN>(a, tile);
         pipe_store<KPAD>(r, Xs, Pw, K);
         __syncthreads();
-        if (tile + step < a.ntiles) pipe_load<KPAD>(a, P, (int)last_tile_col<TN>(a, tile + step), K, r);
+        // ---- middle-mode regulariser taps of this tile's items ----
+        // (summed first: the order of every last-pass variant is the middle
+        // modes, then mode 1, then mode N)
+        vt rmid[IPT];
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+#pragma unroll
+            for (int e = 0; e < E; ++e) rmid[i][e] = Tv(0);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            // items past the last row read row J-1 and are not used
+            const int it = min(threadIdx.x + i * CTA_WG, nitem - 1);
+            const int j = it / GPR;
+            const int c = (it - j * GPR) * E;
+            const int t = t0 + c;
+            const vt pc = *reinterpret_cast<const vt*>(Pw + j * LDP + H + c);
+            const Tv* __restrict__ pb = P + (int64_t)j * trail + t;
+            for (int k = 1; k < N - 1; ++k) {
+                const Tv* __restrict__ rb = st.rband[k];
+                if (!rb) continue;
+                const int sk = (int)st.stride[k], nk = (int)st.ext[k];
+                const int u = fast_div(t, st.smul[k], st.sshift[k]);
+                const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
+                const Tv* br = rb + ik * 5;
+                vt nbv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
+                    const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
+                    nbv[q] = *reinterpret_cast<const vt*>(pb + dd * sk);
+                }
+                rmid[i] += br[2] * pc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rmid[i] += br[q < 2 ? q : q + 1] * nbv[q];
+            }
+        }
         // ---- MFMA (as normal_last_tile with JT = 2, WJ = 4, CT = 2) ----
         {
             const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -768,6 +813,7 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
 #pragma unroll
                 for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
             mfma_cols<bf16, JT, CT>(Xs, ldx, M, a.ldm, 0, jb, KPAD, acc);
+            if (tile + step < a.ntiles) pipe_load<KPAD>(a, P, (int)last_tile_col<TN>(a, tile + step), K, r);
             __syncthreads();  // Xs is dead; its space becomes Qs
 #pragma unroll
             for (int x = 0; x < JT; ++x) {
@@ -783,14 +829,14 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
             }
         }
         __syncthreads();
-        // ---- epilogue (the fast path of normal_last_tile) ----
-        constexpr int GPR = TN / E;
+        // ---- epilogue: modes 1 and N from the LDS window ----
 #pragma unroll 1
-        for (int it = threadIdx.x; it < a.J * GPR; it += CTA_WG) {
+        for (int i = 0; i < IPT; ++i) {
+            const int it = threadIdx.x + i * CTA_WG;
+            if (it >= nitem) break;
             const int j = it / GPR;
             const int c = (it - j * GPR) * E;
             const int t = t0 + c;
-            if (t >= trail) continue;
             const Tv* prow = Pw + j * LDP + H + c;  // prow[0] is P[j][t]
             const int64_t base = (int64_t)j * trail + t;
             // Branch-free taps: a tap outside the tensor has a zero band
@@ -798,9 +844,7 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
             // its address is clamped to a valid one instead of tested.
             const vt pc = *reinterpret_cast<const vt*>(prow);
             vt s = *reinterpret_cast<const vt*>(Qs + j * LDQ + c);  // chain part, lam applied below
-            vt reg;
-#pragma unroll
-            for (int e = 0; e < E; ++e) reg[e] = Tv(0);
+            vt reg = rmid[i];
             if (has1) {
 #pragma unroll
                 for (int d = -2; d <= 2; ++d) {
@@ -825,25 +869,6 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
 #pragma unroll
                     for (int d = -2; d <= 2; ++d) reg[e] += bN[d + 2] * w[E + e + d];
                 }
-            }
-            const Tv* __restrict__ pb = P + base;
-            for (int k = 1; k < N - 1; ++k) {
-                const Tv* __restrict__ rb = st.rband[k];
-                if (!rb) continue;
-                const int sk = (int)st.stride[k], nk = (int)st.ext[k];
-                const int u = fast_div(t, st.smul[k], st.sshift[k]);
-                const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
-                const Tv* br = rb + ik * 5;
-                vt nbv[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
-                    const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
-                    nbv[q] = *reinterpret_cast<const vt*>(pb + dd * sk);
-                }
-                reg += br[2] * pc;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) reg += br[q < 2 ? q : q + 1] * nbv[q];
             }
             const vt qv = s + lam * reg;
             *reinterpret_cast<vt*>(Q + base) = qv;
@@ -1000,6 +1025,26 @@ __device__ __forceinline__ void normal_last_jtile(const StridedArgs& a, int64_t 
             const vt pc = *reinterpret_cast<const vt*>(prow);
             const vt s = *reinterpret_cast<const vt*>(Qs + jr * LDQ + c);
             vt reg = {0.f, 0.f, 0.f, 0.f};
+            // middle modes first, then mode 1, then mode N (the order of every variant)
+            if constexpr (NF) {
+                if (hasF) {
+                    reg += bF[2] * pc;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        reg += bF[q < 2 ? q : q + 1] * *reinterpret_cast<const vt*>(Pf + (q * JB + jr) * TN + c);
+                }
+            }
+            if (hasM) {
+                const int u = fast_div(t, st.smul[N - 2], st.sshift[N - 2]);
+                const int iM = u - fast_div(u, st.emul[N - 2], st.eshift[N - 2]) * gm.nM;
+                const float* br = bM + iM * 5;
+                reg += br[2] * pc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int d = q < 2 ? q - 2 : q - 1;
+                    reg += br[q < 2 ? q : q + 1] * *reinterpret_cast<const vt*>(prow + d * gm.sM);
+                }
+            }
             if (has1) {
 #pragma unroll
                 for (int d = -2; d <= 2; ++d)
@@ -1021,25 +1066,6 @@ __device__ __forceinline__ void normal_last_jtile(const StridedArgs& a, int64_t 
                     const float* bb = bN + (i0 + e) * 5;
 #pragma unroll
                     for (int d = -2; d <= 2; ++d) reg[e] += bb[d + 2] * w[4 + e + d];
-                }
-            }
-            if constexpr (NF) {
-                if (hasF) {
-                    reg += bF[2] * pc;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        reg += bF[q < 2 ? q : q + 1] * *reinterpret_cast<const vt*>(Pf + (q * JB + jr) * TN + c);
-                }
-            }
-            if (hasM) {
-                const int u = fast_div(t, st.smul[N - 2], st.sshift[N - 2]);
-                const int iM = u - fast_div(u, st.emul[N - 2], st.eshift[N - 2]) * gm.nM;
-                const float* br = bM + iM * 5;
-                reg += br[2] * pc;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int d = q < 2 ? q - 2 : q - 1;
-                    reg += br[q < 2 ? q : q + 1] * *reinterpret_cast<const vt*>(prow + d * gm.sM);
                 }
             }
             const vt qv = s + lam * reg;
