@@ -172,6 +172,23 @@ cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
 cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3);
 cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3);
 
+/* Band-aware applies.  Cubic B-spline collocation factors give Gram matrices
+ * G_k with half-bandwidth 3 (Sec. 4: each sample touches 4 basis functions
+ * per mode), so a mode product with G_k is a short stencil along mode k.
+ * cta_op_create records the largest half-bandwidth w of the G_k
+ * (cta_op_band_width); when w <= 4 it keeps the bands in FP64 and FP32 and
+ * turns the banded applies on.  Then every F64 or F32 application of N that
+ * is not part of an inner CG iteration (cta_apply_normal_op with those
+ * chains, the residual updates of the mixed-precision solves, the final
+ * FP64 residual check) runs as N streaming passes: modes N .. 2 as banded
+ * mode products, mode 1 with the regulariser and <P, Q> fused, every sum over
+ * the 2w + 1 taps in ascending offset.  The result equals the dense chain's
+ * up to rounding.  cta_op_set_banded(op, 0) restores the dense passes;
+ * enabling fails with CTA_ERR_ARG when w > 4.  Returns of cta_op_band_width:
+ * w, or -1 for a NULL handle. */
+cta_status cta_op_set_banded(cta_op op, int enable);
+int cta_op_band_width(cta_op op);
+
 /* Tensor-inverse preconditioner (Sec. 3: a separable operator is inverted
  * mode by mode).  The separable part of N with each G_k replaced by
  * G_k + c R_k is inverted per mode:

@@ -99,6 +99,8 @@ _SIGS = {
     "cta_tune_op": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P]),
     "cta_op_get_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "cta_op_set_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "cta_op_set_banded": (ctypes.c_int, [_P, ctypes.c_int]),
+    "cta_op_band_width": (ctypes.c_int, [_P]),
     "cta_prof_enable": (ctypes.c_int, [ctypes.c_int]),
     "cta_prof_reset": (ctypes.c_int, []),
     "cta_prof_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t,
@@ -114,6 +116,11 @@ def load_library(path=None):
     path = path or library_path()
     if not os.path.exists(path):
         raise CtaError(-7, f"{path} not found: build it with paper_1001_5460_amd.build")
+    # torch first: libcta then binds to the HIP runtime torch already loaded,
+    # so the process has one runtime and torch's streams and memory are
+    # valid in the library (loaded first, libcta would pull in a second
+    # runtime that holds the device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
@@ -327,6 +334,14 @@ def cta_tune_op(h, chain="bf16", reps=5, stream=None):
     return {"tail": v[0], "middle": v[1], "last": v[2]}
 
 
+def cta_op_set_banded(h, enable):
+    _check(load_library().cta_op_set_banded(h, int(enable)))
+
+
+def cta_op_band_width(h):
+    return load_library().cta_op_band_width(h)
+
+
 def cta_op_set_tuning(h, chain, tail, middle, last):
     v = (ctypes.c_int * 3)(tail, middle, last)
     _check(load_library().cta_op_set_tuning(h, _PREC[chain], v))
@@ -505,6 +520,13 @@ class Operator:
         if Q is None:
             Q = torch.empty_like(P)
         return cta_apply_normal_op(self.handle, P, Q, chain, dot, stream)
+
+    def set_banded(self, enable):
+        cta_op_set_banded(self.handle, enable)
+
+    @property
+    def band_width(self):
+        return cta_op_band_width(self.handle)
 
     def tune(self, chain="bf16", reps=5, stream=None):
         return cta_tune_op(self.handle, chain, reps, stream)

@@ -48,6 +48,13 @@ struct cta_op_s {
     cta::Mat Pinv[3][CTA_MAX_ORDER];
     bool has_pc = false;
     double pc_c = 0.0;
+    // banded Grams: half-bandwidth band_w <= 4 of every G_k, bands per dtype
+    // (F64, F32); use_band routes the F64/F32 applies without fused CG
+    // updates through the banded passes
+    bool band_ok = false;
+    bool use_band = false;
+    int band_w = -1;
+    void* gband[2][CTA_MAX_ORDER] = {{nullptr}};
 };
 
 namespace cta {

@@ -112,9 +112,48 @@ static int prec_tvec(int prec) { return prec == CTA_PREC_F64 ? DT_F64 : DT_F32; 
 //   pass A: tail on modes (N-2, N-1) of P (optionally fused with p = r + beta p)
 //   middle: strided passes on modes N-3 .. 1
 //   last  : mode 0 with the banded regulariser of P and <P, Q>
+// Q = N(P) through the banded passes (F64 or F32, no fused CG update).
+static cta_status apply_normal_band(cta_op_s* op, const void* P, void* Q, int prec, int post,
+                                    double* dot_out, hipStream_t s) {
+    const int N = op->order;
+    const int dt = prec == CTA_PREC_F64 ? DT_F64 : DT_F32;
+    const int bi = dt == DT_F64 ? 0 : 1;
+    const void* cur = P;
+    void* outs[2] = {op->T1, op->T2};
+    int o = 0;
+    for (int k = N - 1; k >= 1; --k) {
+        int64_t lead = 1, trail = 1;
+        for (int l = 0; l < k; ++l) lead *= op->n[l];
+        for (int l = k + 1; l < N; ++l) trail *= op->n[l];
+        hipError_t e = launch_band_mode(dt, cur, outs[o], op->gband[bi][k], op->band_w, lead, (int)op->n[k],
+                                        trail, s);
+        if (e != hipSuccess) return fail(CTA_ERR_HIP, "banded mode pass launch: %s", hipGetErrorString(e));
+        cur = outs[o];
+        o ^= 1;
+    }
+    StencilDesc st{};
+    st.P = P;
+    st.order = N;
+    st.lam = op->lam;
+    int64_t stride = 1;
+    for (int k = N - 1; k >= 0; --k) {
+        st.ext[k] = op->n[k];
+        st.stride[k] = stride;
+        stride *= op->n[k];
+        st.rband[k] = op->rband[bi][k];
+    }
+    hipError_t e = launch_band_last(dt, cur, Q, op->gband[bi][0], op->band_w, (int)op->n[0], op->N / op->n[0],
+                                    st, op->partials, op->scal, post, dot_out, s);
+    if (e != hipSuccess) return fail(CTA_ERR_HIP, "banded last pass launch: %s", hipGetErrorString(e));
+    return CTA_OK;
+}
+
 cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post,
                         double* dot_out, bool fuse_update, hipStream_t s, void* xsol,
                         const void* fuse_src) {
+    if (op->use_band && !fuse_update && (prec == CTA_PREC_F64 || prec == CTA_PREC_F32) &&
+        (post == POST_NONE || post == POST_DOT))
+        return apply_normal_band(op, P, Q, prec, post, dot_out, s);
     const int N = op->order;
     const int tc = prec_tc(prec), tv = prec_tvec(prec);
     const int* done = fuse_update ? &op->scal->done : nullptr;
@@ -402,6 +441,40 @@ extern "C" cta_status cta_op_create(cta_op* out, int order, const int64_t* n, co
                 (hipMemcpy(op->rband[0][k], band64.data(), band64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
                  hipMemcpy(op->rband[1][k], band32.data(), band32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
                 st = fail(CTA_ERR_HIP, "copy of regulariser bands failed");
+        }
+    }
+    // banded Grams (B-spline collocation gives half-bandwidth 3): the band of
+    // every G_k when all are within half-bandwidth kBandMax
+    if (st == CTA_OK) {
+        constexpr int kBandMax = 4;
+        int w = 0;
+        for (int k = 0; k < op->order; ++k) {
+            const int nk = (int)op->n[k];
+            for (int i = 0; i < nk; ++i)
+                for (int j = 0; j < nk; ++j)
+                    if (G[k][(size_t)i * nk + j] != 0.0) w = std::max(w, std::abs(i - j));
+        }
+        op->band_w = w;
+        if (w <= kBandMax) {
+            const int wd = 2 * w + 1;
+            for (int k = 0; k < op->order && st == CTA_OK; ++k) {
+                const int nk = (int)op->n[k];
+                std::vector<double> b64((size_t)nk * wd, 0.0);
+                std::vector<float> b32((size_t)nk * wd, 0.f);
+                for (int i = 0; i < nk; ++i)
+                    for (int d = -w; d <= w; ++d)
+                        if (i + d >= 0 && i + d < nk) {
+                            b64[(size_t)i * wd + d + w] = G[k][(size_t)i * nk + i + d];
+                            b32[(size_t)i * wd + d + w] = (float)G[k][(size_t)i * nk + i + d];
+                        }
+                st = dev_alloc(&op->gband[0][k], b64.size() * 8, al, acc);
+                if (st == CTA_OK) st = dev_alloc(&op->gband[1][k], b32.size() * 4, al, acc);
+                if (st == CTA_OK &&
+                    (hipMemcpy(op->gband[0][k], b64.data(), b64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+                     hipMemcpy(op->gband[1][k], b32.data(), b32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+                    st = fail(CTA_ERR_HIP, "copy of the Gram bands failed");
+            }
+            op->band_ok = op->use_band = st == CTA_OK && op->N < ((int64_t)1 << 30);
         }
     }
     const size_t vb = (size_t)op->N * 8;
@@ -889,6 +962,16 @@ extern "C" cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const in
     op->var_last[tc] = host_variants3[2];
     return CTA_OK;
 }
+
+extern "C" cta_status cta_op_set_banded(cta_op op, int enable) {
+    if (!op) return fail(CTA_ERR_ARG, "NULL operator");
+    if (enable && !op->band_ok)
+        return fail(CTA_ERR_ARG, "the Gram factors are not banded (half-bandwidth %d > 4)", op->band_w);
+    op->use_band = enable != 0;
+    return CTA_OK;
+}
+
+extern "C" int cta_op_band_width(cta_op op) { return op ? op->band_w : -1; }
 
 // ---------------------------------------------------------------------------
 // Tensor-inverse preconditioner: (G_k + c R_k)^-1 per mode, by Cholesky

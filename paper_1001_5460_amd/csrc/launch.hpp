@@ -100,6 +100,15 @@ hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q
                               double* partials, CgScalars* scal, int post, double* dot_out,
                               const int* done, hipStream_t s, int variant = 0);
 
+// ---- band-aware normal operator (F64 or F32; half-bandwidth w <= 4) ----
+// Y = X x_k G on the (lead, K, trail) view with gb[j * (2w+1) + d + w] = G[j][j+d].
+hipError_t launch_band_mode(int dt, const void* X, void* Y, const void* gb, int w, int64_t lead, int K,
+                            int64_t trail, hipStream_t s);
+// Q = X x_1 G_1 (banded) + lam * regulariser(P) and <P, Q> partials (then `post`).
+hipError_t launch_band_last(int dt, const void* X, void* Q, const void* gb, int w, int K, int64_t trail,
+                            const StencilDesc& st, double* partials, CgScalars* scal, int post,
+                            double* dot_out, hipStream_t s);
+
 // ---- vector kernels (Tv = F32 or F64) ----
 hipError_t launch_cast(int tin, int tout, const void* x, void* y, int64_t n, hipStream_t s);
 hipError_t launch_fill_zero(void* x, int64_t bytes, hipStream_t s);
