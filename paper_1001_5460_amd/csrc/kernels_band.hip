@@ -202,6 +202,7 @@ __global__ __launch_bounds__(CTA_WG) void k_band_last(BandLastArgs<T> a) {
 #pragma unroll
                 for (int d = -2; d <= 2; ++d) reg += br[d + 2] * pw[i + d + 2];
             }
+            const vt pc = pw[i + 2];
             for (int k = 1; k < N - 1; ++k) {
                 const T* __restrict__ rb = a.rband[k];
                 if (!rb) continue;
@@ -211,12 +212,33 @@ __global__ __launch_bounds__(CTA_WG) void k_band_last(BandLastArgs<T> a) {
                 const T* __restrict__ br = rb + ik * 5;
 #pragma unroll
                 for (int d = -2; d <= 2; ++d) {
-                    const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
-                    reg += br[d + 2] * ldv<T, V>(a.P + base + (int64_t)dd * sk);
+                    if (d == 0) {
+                        reg += br[2] * pc;
+                    } else {
+                        const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
+                        reg += br[d + 2] * ldv<T, V>(a.P + base + (int64_t)dd * sk);
+                    }
                 }
             }
             if (rbN) {
-                // contiguous mode: per-element band rows, taps at +-1, +-2
+                // contiguous mode: per-element band rows, taps at +-1, +-2,
+                // read as the vectors before, at and after the unit (clamped
+                // at the ends of the tensor, where the coefficients are zero)
+                constexpr int L = V >= 2 ? V : 2;
+                T w[3 * L];
+                if constexpr (V >= 2) {
+                    const vt pl = ldv<T, V>(a.P + max(base - V, (int64_t)0));
+                    const vt pr = ldv<T, V>(a.P + min(base + V, a.total - V));
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        w[e] = pl[e];
+                        w[L + e] = pc[e];
+                        w[2 * L + e] = pr[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int d = -2; d <= 3; ++d) w[L + d] = a.P[min(max(base + d, (int64_t)0), a.total - 1)];
+                }
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     int ie = i0 + e;
@@ -224,10 +246,7 @@ __global__ __launch_bounds__(CTA_WG) void k_band_last(BandLastArgs<T> a) {
                     const T* __restrict__ br = rbN + ie * 5;
                     T sum = T(0);
 #pragma unroll
-                    for (int d = -2; d <= 2; ++d) {
-                        const int64_t idx = min(max(base + e + d, (int64_t)0), a.total - 1);
-                        sum += br[d + 2] * a.P[idx];
-                    }
+                    for (int d = -2; d <= 2; ++d) sum += br[d + 2] * w[L + e + d];
                     if constexpr (V == 1)
                         reg += sum;
                     else
@@ -236,7 +255,6 @@ __global__ __launch_bounds__(CTA_WG) void k_band_last(BandLastArgs<T> a) {
             }
             const vt qv = acc + lam * reg;
             stv<T, V>(a.Q + base, qv);
-            const vt pc = pw[i + 2];
             if constexpr (V == 1) {
                 dot += (double)pc * (double)qv;
             } else {
