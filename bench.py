@@ -12,8 +12,9 @@ FP64 on the GPU (reliable updates, or restarted refinement with
 
 Printed: one JSON line.  `value` = CG iterations per second over the timed
 steps (all inner iterations of the refinement); also the time to 1e-8, the
-TTM-chain TFLOP/s (2 * N * sum_k n_k flops per operator apply, plus the
-right-hand-side chain), the dominant kernel's roofline fraction (timed live
+TTM-chain TFLOP/s (2 * N * sum_k n_k flops per dense operator apply, plus the
+right-hand-side chain; residual updates that run as banded passes are left
+out), the dominant kernel's roofline fraction (timed live
 with HIP events by the library's tracer), the oracle timed on the host, the
 plain FP32 CG comparison and the oracle's FP64 residual judge of the solution.
 
@@ -99,6 +100,12 @@ def algorithmic(name, N, n):
         "tail.f64": (N * (8 + 8), 2 * N * (n[2] + n[3])),
         "strided.f64": (N * (8 + 8), 2 * N * n[1]),
         "normal_last.f64": (N * (8 + 8 + 8), 2 * N * n[0]),
+        # banded passes (residual updates): one mode product, or the mode-1 pass
+        # with the regulariser and <P,Q> (reads T and P, writes Q)
+        "band_mode.f64": (N * (8 + 8), 0),
+        "band_last.f64": (N * (8 + 8 + 8), 0),
+        "band_mode.f32": (N * (4 + 4), 0),
+        "band_last.f32": (N * (4 + 4 + 4), 0),
         "residual.f64_f32": (N * (8 + 8 + 4), 0),
         "add_f64": (N * (8 + 4 + 8), 0),
         "dot.f32": (N * 4, 0),
@@ -474,7 +481,11 @@ def main():
     apply_flops = 2 * N * sn
     rhs_flops = chain_flops_rect(p.m, p.n)
     # BF16 applies = inner iterations; FP64 applies = one per refinement step + the initial residual
-    chain_flops = iters * apply_flops + (refine + args.steps) * apply_flops + args.steps * rhs_flops
+    # residual updates run as banded passes when the Grams are banded; those do
+    # n_k / (2w + 1) of the dense flops and are left out of the dense-TTM figure
+    banded = op.band_width <= 4
+    chain_flops = (iters * apply_flops + (0 if banded else (refine + args.steps) * apply_flops)
+                   + args.steps * rhs_flops)
     chain_kernels = [k for k in prof if k.split(".")[0] in ("tail_p", "tail", "strided", "normal_last", "contig")]
     chain_ms = sum(prof[k]["total_ms"] for k in chain_kernels)
 
@@ -550,6 +561,7 @@ def main():
         "refine_steps_per_solve": refine / args.steps,
         "rel_res_true": max(i["rel_res_true"] for i in infos),
         "converged": ok,
+        "banded_updates": {"gram_half_bandwidth": op.band_width, "on": banded},
         "ttm_chain_tflops": round(chain_flops / elapsed / 1e12, 2),
         "ttm_chain_tflops_in_kernels": round(chain_flops / (chain_ms / 1e3) / 1e12, 2) if chain_ms else None,
         "roofline": roof,
