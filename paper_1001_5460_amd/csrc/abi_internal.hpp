@@ -55,10 +55,30 @@ struct cta_op_s {
     bool use_band = false;
     int band_w = -1;
     void* gband[2][CTA_MAX_ORDER] = {{nullptr}};
+    // banded rows of A_k (direction 0, forward model) and A_k^T (direction 1,
+    // right-hand side): first column and w coefficients per row, per dtype
+    bool cb_ok[2] = {false, false};
+    int cb_w[2] = {0, 0};
+    int* cb_lo[2][CTA_MAX_ORDER] = {{nullptr}};
+    void* cb_coef[2][2][CTA_MAX_ORDER] = {{{nullptr}}};
 };
 
 namespace cta {
 cta_status fail(cta_status st, const char* fmt, ...);
+// Banded factors of a rectangular chain: per mode, the first column of each
+// row and w coefficients per row (device pointers).
+struct ChainBand {
+    int w = 0;
+    const int* lo[CTA_MAX_ORDER] = {nullptr};
+    const void* coef[CTA_MAX_ORDER] = {nullptr};
+};
+std::vector<int> plan_order(int N, const int64_t* in_ext, const int64_t* out_ext,
+                            const std::vector<int>& modes, int64_t* max_elems);
+// Y = X x_k M_k over `order` (mode products on modes in that order); with
+// `band`, each pass uses the banded rows instead of the dense M_k.
+cta_status run_chain(int N, const int64_t* in_ext, const int64_t* out_ext, const Mat* mats,
+                     const std::vector<int>& order, const void* X, int tin, void* Y, int tout,
+                     int tc, void* w0, void* w1, hipStream_t s, const ChainBand* band = nullptr);
 // Q = N(P).  fuse_update: the chain input is p = r + beta p (op->vr, op->vp),
 // and with xsol the previous CG step's xsol += alpha p is applied on the
 // same pass.

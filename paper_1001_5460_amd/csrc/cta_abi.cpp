@@ -287,7 +287,7 @@ std::vector<int> plan_order(int N, const int64_t* in_ext, const int64_t* out_ext
 // the two work buffers (each >= max intermediate elements * size(tc)).
 cta_status run_chain(int N, const int64_t* in_ext, const int64_t* out_ext, const Mat* mats,
                      const std::vector<int>& order, const void* X, int tin, void* Y, int tout,
-                     int tc, void* w0, void* w1, hipStream_t s) {
+                     int tc, void* w0, void* w1, hipStream_t s, const ChainBand* band) {
     int64_t cur[CTA_MAX_ORDER];
     int64_t tot = 1;
     for (int k = 0; k < N; ++k) {
@@ -314,7 +314,12 @@ cta_status run_chain(int N, const int64_t* in_ext, const int64_t* out_ext, const
         for (int l = 0; l < k; ++l) lead *= cur[l];
         for (int l = k + 1; l < N; ++l) trail *= cur[l];
         const int K = (int)cur[k], J = (int)out_ext[k];
-        if (trail == 1)
+        // the contiguous mode keeps the MFMA pass, which is faster there than
+        // the banded one (rows of K contiguous elements are MFMA operands as
+        // loaded)
+        if (band && trail > 1)
+            e = launch_rect_band(tc, src, dst, band->lo[k], band->coef[k], band->w, lead, K, J, trail, s);
+        else if (trail == 1)
             e = launch_contig(tc, src, dst, mats[k], lead, K, J, nullptr, s);
         else
             e = launch_strided(tc, src, dst, mats[k], lead, K, J, trail, nullptr, s);
@@ -477,6 +482,57 @@ extern "C" cta_status cta_op_create(cta_op* out, int order, const int64_t* n, co
             op->band_ok = op->use_band = st == CTA_OK && op->N < ((int64_t)1 << 30);
         }
     }
+    // banded rows of A_k and A_k^T for the forward and right-hand-side chains:
+    // the span of each row's nonzeros, rounded up to 4, 6 or 8 columns
+    for (int dir = 0; dir < 2 && st == CTA_OK && op->band_ok; ++dir) {
+        int wmax = 0;
+        std::vector<std::vector<int>> los(op->order);
+        for (int k = 0; k < op->order; ++k) {
+            const int nk = (int)op->n[k], mk = (int)op->m[k];
+            const int rows = dir == 0 ? mk : nk, cols = dir == 0 ? nk : mk;
+            los[k].assign(rows, 0);
+            for (int r = 0; r < rows; ++r) {
+                int first = -1, last = -1;
+                for (int c = 0; c < cols; ++c) {
+                    const double v = dir == 0 ? A[k][(size_t)r * nk + c] : A[k][(size_t)c * nk + r];
+                    if (v != 0.0) {
+                        if (first < 0) first = c;
+                        last = c;
+                    }
+                }
+                los[k][r] = first < 0 ? 0 : first;
+                wmax = std::max(wmax, first < 0 ? 0 : last - first + 1);
+            }
+        }
+        if (wmax > 8) continue;
+        const int w = wmax <= 4 ? 4 : wmax <= 6 ? 6 : 8;
+        for (int k = 0; k < op->order && st == CTA_OK; ++k) {
+            const int nk = (int)op->n[k], mk = (int)op->m[k];
+            const int rows = dir == 0 ? mk : nk, cols = dir == 0 ? nk : mk;
+            std::vector<double> c64((size_t)rows * w, 0.0);
+            std::vector<float> c32((size_t)rows * w, 0.f);
+            for (int r = 0; r < rows; ++r)
+                for (int c = 0; c < w; ++c) {
+                    const int col = los[k][r] + c;
+                    if (col >= cols) continue;
+                    const double v = dir == 0 ? A[k][(size_t)r * nk + col] : A[k][(size_t)col * nk + r];
+                    c64[(size_t)r * w + c] = v;
+                    c32[(size_t)r * w + c] = (float)v;
+                }
+            st = dev_alloc((void**)&op->cb_lo[dir][k], (size_t)rows * 4, al, acc);
+            if (st == CTA_OK) st = dev_alloc(&op->cb_coef[dir][0][k], c64.size() * 8, al, acc);
+            if (st == CTA_OK) st = dev_alloc(&op->cb_coef[dir][1][k], c32.size() * 4, al, acc);
+            if (st == CTA_OK &&
+                (hipMemcpy(op->cb_lo[dir][k], los[k].data(), (size_t)rows * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(op->cb_coef[dir][0][k], c64.data(), c64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(op->cb_coef[dir][1][k], c32.data(), c32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+                st = fail(CTA_ERR_HIP, "copy of the factor bands failed");
+        }
+        if (st == CTA_OK) {
+            op->cb_ok[dir] = true;
+            op->cb_w[dir] = w;
+        }
+    }
     const size_t vb = (size_t)op->N * 8;
     void** vecs[] = {&op->T1, &op->T2, &op->vx, &op->vr, &op->vp, &op->vq, &op->vaux};
     for (void** v : vecs)
@@ -540,8 +596,19 @@ static cta_status op_chain(cta_op op, const void* X, cta_dtype xd, void* Y, cta_
     const int64_t* out_ext = forward ? op->m : op->n;
     std::vector<int> order = plan_order(N, in_ext, out_ext, modes, nullptr);
     const Mat* mats = forward ? op->A[tc == DT_F64 ? 0 : 1] : op->At[tc == DT_F64 ? 0 : 1];
+    // banded factors (B-spline collocation): streaming banded passes
+    const int dir = forward ? 0 : 1;
+    ChainBand band{};
+    const bool banded = op->use_band && op->cb_ok[dir];
+    if (banded) {
+        band.w = op->cb_w[dir];
+        for (int k = 0; k < N; ++k) {
+            band.lo[k] = op->cb_lo[dir][k];
+            band.coef[k] = op->cb_coef[dir][tc == DT_F64 ? 0 : 1][k];
+        }
+    }
     return run_chain(N, in_ext, out_ext, mats, order, X, (int)xd, Y, (int)yd, tc, op->rw0, op->rw1,
-                     (hipStream_t)stream);
+                     (hipStream_t)stream, banded ? &band : nullptr);
 }
 
 extern "C" cta_status cta_forward(cta_op op, const void* X, cta_dtype x_dtype, void* Y,

@@ -344,3 +344,86 @@ hipError_t launch_band_last(int dt, const void* X, void* Q, const void* gb, int 
 }
 
 }  // namespace cta
+
+namespace cta {
+
+// ---------------------------------------------------------------------------
+// Banded rectangular mode product for the forward model and the right-hand
+// side (Sec. 4: a sample touches 4 consecutive B-spline basis functions per
+// mode, and a basis function a short run of consecutive samples):
+// Y[b, j, t] = sum_{c < W} coef[j * W + c] * X[b, lo[j] + c, t] on the
+// (lead, K -> J, trail) view.  Rows past K have zero coefficients and clamped
+// addresses.  A unit is V consecutive t of one (b, j).
+struct RectBandArgs {
+    const void* X;
+    void* Y;
+    const int* lo;
+    const void* coef;
+    int K, J;
+    int64_t trail;
+    int64_t nunit;       // lead * J * trail / V  (< 2^30)
+    uint32_t tmul, jmul;
+    int tshift, jshift;  // division by trail / V and by J
+};
+
+template <typename T, int W, int V>
+__global__ __launch_bounds__(CTA_WG) void k_rect_band(RectBandArgs a) {
+    typedef typename VecT<T, V>::type vt;
+    const T* __restrict__ X = reinterpret_cast<const T*>(a.X);
+    T* __restrict__ Y = reinterpret_cast<T*>(a.Y);
+    const T* __restrict__ cf = reinterpret_cast<const T*>(a.coef);
+    const int ntv = (int)(a.trail / V);
+    for (int u = blockIdx.x * CTA_WG + threadIdx.x; u < (int)a.nunit; u += gridDim.x * CTA_WG) {
+        const int q = fast_div(u, a.tmul, a.tshift);      // b * J + j
+        const int tv = u - q * ntv;
+        const int b = fast_div(q, a.jmul, a.jshift);
+        const int j = q - b * a.J;
+        const int lo = a.lo[j];
+        const T* __restrict__ xb = X + ((int64_t)b * a.K) * a.trail + (int64_t)tv * V;
+        const T* __restrict__ c = cf + j * W;
+        vt acc = vt(0);
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const int k = min(lo + i, a.K - 1);
+            acc += c[i] * ldv<T, V>(xb + (int64_t)k * a.trail);
+        }
+        stv<T, V>(Y + (int64_t)q * a.trail + (int64_t)tv * V, acc);
+    }
+}
+
+template <typename T, int W>
+static hipError_t rect_band_T(RectBandArgs a, int64_t lead, hipStream_t s) {
+    constexpr int V = 16 / sizeof(T);
+    const bool vec = a.trail % V == 0;
+    const int v = vec ? V : 1;
+    a.nunit = lead * a.J * (a.trail / v);
+    if (a.nunit >= ((int64_t)1 << 30) || lead * a.K * a.trail >= ((int64_t)1 << 31))
+        return hipErrorInvalidValue;
+    fastdiv_init((uint32_t)(a.trail / v), &a.tmul, &a.tshift);
+    fastdiv_init((uint32_t)a.J, &a.jmul, &a.jshift);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a.nunit + CTA_WG - 1) / CTA_WG, 65536));
+    if (vec)
+        k_rect_band<T, W, V><<<grid, CTA_WG, 0, s>>>(a);
+    else
+        k_rect_band<T, W, 1><<<grid, CTA_WG, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rect_band(int dt, const void* X, void* Y, const int* lo, const void* coef, int w,
+                            int64_t lead, int K, int J, int64_t trail, hipStream_t s) {
+    RectBandArgs a{};
+    a.X = X; a.Y = Y; a.lo = lo; a.coef = coef; a.K = K; a.J = J; a.trail = trail;
+    ProfScope ps(dt == DT_F64 ? "rect_band.f64" : "rect_band.f32", s);
+#define CTA_RECT_W(TT)                                                   \
+    switch (w) {                                                         \
+        case 4: return rect_band_T<TT, 4>(a, lead, s);                   \
+        case 6: return rect_band_T<TT, 6>(a, lead, s);                   \
+        case 8: return rect_band_T<TT, 8>(a, lead, s);                   \
+    }
+    if (dt == DT_F64) CTA_RECT_W(double)
+    if (dt == DT_F32) CTA_RECT_W(float)
+#undef CTA_RECT_W
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cta

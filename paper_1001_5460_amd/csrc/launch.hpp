@@ -109,6 +109,11 @@ hipError_t launch_band_last(int dt, const void* X, void* Q, const void* gb, int 
                             const StencilDesc& st, double* partials, CgScalars* scal, int post,
                             double* dot_out, hipStream_t s);
 
+// Y = X x_k M for a matrix whose row j has its nonzeros in columns lo[j] ..
+// lo[j] + w - 1 (coef[j * w + c] = M[j][lo[j] + c], w in {4, 6, 8}).
+hipError_t launch_rect_band(int dt, const void* X, void* Y, const int* lo, const void* coef, int w,
+                            int64_t lead, int K, int J, int64_t trail, hipStream_t s);
+
 // ---- vector kernels (Tv = F32 or F64) ----
 hipError_t launch_cast(int tin, int tout, const void* x, void* y, int64_t n, hipStream_t s);
 hipError_t launch_fill_zero(void* x, int64_t bytes, hipStream_t s);

@@ -10,14 +10,6 @@
 
 using namespace cta;
 
-namespace cta {
-std::vector<int> plan_order(int N, const int64_t* in_ext, const int64_t* out_ext,
-                            const std::vector<int>& modes, int64_t* max_elems);
-cta_status run_chain(int N, const int64_t* in_ext, const int64_t* out_ext, const Mat* mats,
-                     const std::vector<int>& order, const void* X, int tin, void* Y, int tout,
-                     int tc, void* w0, void* w1, hipStream_t s);
-}  // namespace cta
-
 namespace {
 
 struct TtmPlan {

@@ -109,3 +109,29 @@ def test_reliable_solve_with_banded_updates(banded):
     assert info["status"] == 0, info
     res = oracle.relative_residual(host(X), B, ref)
     assert res <= 1.01e-8, res
+
+
+@pytest.mark.parametrize("chain", ["f64", "f32"])
+@pytest.mark.parametrize("n,m,lam", PROBLEMS)
+def test_banded_forward_and_rhs_vs_oracle_and_dense(n, m, lam, chain):
+    """Forward model X x_k A_k and right-hand side Y x_k A_k^T with the banded
+    rows of the collocation factors, against the oracle and the dense chain."""
+    torch = torch_cuda()
+    p = _problem(n, m, lam)
+    ref = oracle.NormalOperator(p.A, p.D, p.lam)
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal(n)
+    Y = rng.standard_normal(m)
+    op = cta.Operator(p.A, p.D, p.lam)
+    dt = torch.float64 if chain == "f64" else torch.float32
+    out = {}
+    for banded in (True, False):
+        op.set_banded(banded)
+        out[banded] = (host(op.forward(dev(X, dt), chain=chain)), host(op.rhs(dev(Y, dt), chain=chain)))
+    want_f, want_b = ref.forward(X), ref.rhs(Y)
+    # four mode products per chain: four times the single-product FP32 budget
+    tol = {"f64": 1e-12, "f32": 4e-5}[chain]
+    assert rel_fro(out[True][0], want_f) <= tol
+    assert rel_fro(out[True][1], want_b) <= tol
+    assert rel_fro(out[True][0], out[False][0]) <= 2 * tol
+    assert rel_fro(out[True][1], out[False][1]) <= 2 * tol
