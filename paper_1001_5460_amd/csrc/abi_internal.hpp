@@ -88,6 +88,9 @@ cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post
 // Z = M^-1(R) (the tensor-inverse preconditioner) with <R, Z> reduced on the
 // device and handled by `post`; gated: every kernel exits when the solve's
 // done flag is set.
+// fuse_r (BF16 chain, inside the preconditioned iteration): R is the residual
+// r, updated as r -= alpha q (q = op->vq) by the first pass, which also forms
+// <r, r> and the stopping test (POST_RHO) before the rest of the chain.
 cta_status apply_precond(cta_op_s* op, const void* R, void* Z, int prec, int post, double* dot_out,
-                         bool gated, hipStream_t s);
+                         bool gated, hipStream_t s, bool fuse_r = false);
 }  // namespace cta

@@ -208,16 +208,26 @@ cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post
 // the normal operator (fused tail, strided middle modes, last pass) with no
 // regulariser in the last pass, whose FP64 dot gives <R, Z>.
 cta_status apply_precond(cta_op_s* op, const void* R, void* Z, int prec, int post, double* dot_out,
-                         bool gated, hipStream_t s) {
+                         bool gated, hipStream_t s, bool fuse_r) {
     if (!op->has_pc) return fail(CTA_ERR_ARG, "no preconditioner: call cta_op_set_preconditioner first");
     const int N = op->order;
     const int tc = prec_tc(prec), tv = prec_tvec(prec);
     const int* done = gated ? &op->scal->done : nullptr;
     const int a = N - 2, b = N - 1;
     const int64_t nblk = op->N / (op->n[a] * op->n[b]);
-    hipError_t e = launch_tail(tv, tc, tc, R, op->T1, op->Pinv[tc][a], op->Pinv[tc][b], nblk,
-                               (int)op->n[a], (int)op->n[b], (int)op->n[a], (int)op->n[b], nullptr,
-                               nullptr, done, s, op->var_tail[tc]);
+    hipError_t e;
+    if (fuse_r) {
+        // R is the residual: r -= alpha q (q in op->vq), <r, r> and the
+        // stopping test in the same pass (BF16 chain)
+        if (tc != DT_BF16) return fail(CTA_ERR_ARG, "the fused residual update needs the BF16 chain");
+        e = launch_tail_r(const_cast<void*>(R), op->vq, op->T1, op->Pinv[tc][a], op->Pinv[tc][b], nblk,
+                          (int)op->n[a], (int)op->n[b], (int)op->n[a], (int)op->n[b], &op->scal->alpha, done,
+                          op->partials, op->scal, s, op->var_tail[tc]);
+    } else {
+        e = launch_tail(tv, tc, tc, R, op->T1, op->Pinv[tc][a], op->Pinv[tc][b], nblk, (int)op->n[a],
+                        (int)op->n[b], (int)op->n[a], (int)op->n[b], nullptr, nullptr, done, s,
+                        op->var_tail[tc]);
+    }
     if (e != hipSuccess) return fail(CTA_ERR_HIP, "preconditioner tail launch: %s", hipGetErrorString(e));
     void* cur = op->T1;
     void* nxt = op->T2;
@@ -686,8 +696,13 @@ cta_status cg_loop(cta_op_s* op, void* x, int prec, double rtol, int max_iter, i
         for (int c = 0; c < check_every; ++c) {
             CTA_TRY(apply_normal(op, nullptr, op->vq, prec, POST_ALPHA, nullptr, true, s, x,
                                  pc ? op->vaux : nullptr));
-            CTA_HIP(launch_cg_update(tv, nullptr, op->vr, op->vp, op->vq, op->N, op->partials, op->scal, s));
-            if (pc) CTA_TRY(apply_precond(op, op->vr, op->vaux, prec, POST_RZ, nullptr, true, s));
+            if (pc && prec == CTA_PREC_BF16) {
+                // r -= alpha q fused into the preconditioner's first pass
+                CTA_TRY(apply_precond(op, op->vr, op->vaux, prec, POST_RZ, nullptr, true, s, true));
+            } else {
+                CTA_HIP(launch_cg_update(tv, nullptr, op->vr, op->vp, op->vq, op->N, op->partials, op->scal, s));
+                if (pc) CTA_TRY(apply_precond(op, op->vr, op->vaux, prec, POST_RZ, nullptr, true, s));
+            }
         }
         CTA_TRY(read_scal(op, s));
         if (op->hscal->done != DONE_RUNNING) break;
@@ -858,10 +873,14 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
                     for (int c = 0; c < chunk; ++c) {
                         CTA_TRY(apply_normal(op, nullptr, op->vq, CTA_PREC_BF16, POST_ALPHA, nullptr, true, s,
                                              op->vx, pc ? op->vaux : nullptr));
-                        CTA_HIP(launch_cg_update(DT_F32, nullptr, op->vr, op->vp, op->vq, n, op->partials,
-                                                 op->scal, s));
-                        if (pc)
-                            CTA_TRY(apply_precond(op, op->vr, op->vaux, CTA_PREC_BF16, POST_RZ, nullptr, true, s));
+                        if (pc) {
+                            // r -= alpha q fused into the preconditioner's first pass
+                            CTA_TRY(apply_precond(op, op->vr, op->vaux, CTA_PREC_BF16, POST_RZ, nullptr, true, s,
+                                                  true));
+                        } else {
+                            CTA_HIP(launch_cg_update(DT_F32, nullptr, op->vr, op->vp, op->vq, n, op->partials,
+                                                     op->scal, s));
+                        }
                     }
                     CTA_TRY(read_scal(op, s));
                     gdone = op->hscal->done;

@@ -488,6 +488,57 @@ hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const 
     return hipErrorInvalidValue;
 }
 
+// Tail pass of the preconditioner with the residual update fused (BF16 chain):
+// r = r - alpha q is formed on the fly, written back, fed to the chain, and
+// <r, r> is reduced (partials, then the finalize kernel with POST_RHO).
+template <int J2T>
+__global__ __launch_bounds__(CTA_WG) void k_tail_r(TailArgs a) {
+    if (a.done && *a.done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[CTA_WAVES];
+    double dot = 0.0;
+    const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int64_t blk0 = grp * a.nbg;
+        const int nb = (int)std::min<int64_t>(a.nbg, a.nblk - blk0);
+        tail_group<float, bf16, bf16, J2T, false, true>(a, blk0, nb, a.nbg, smem, &dot);
+    }
+    block_partial(dot, a.partials, red);
+}
+
+hipError_t launch_tail_r(void* R, const void* Q, void* Y, const Mat& M1, const Mat& M2, int64_t nblk, int K1,
+                         int K2, int J1, int J2, const double* alpha, const int* done, double* partials,
+                         CgScalars* scal, hipStream_t s, int variant) {
+    if (!tail_fits(DT_BF16, K1, J2) || J1 > 256) return hipErrorInvalidValue;
+    const int ks = dt_kstep(DT_BF16);
+    TailArgs a{};
+    a.X = R; a.Y = Y; a.M1 = M1.p; a.M2 = M2.p; a.ldm1 = M1.ld; a.ldm2 = M2.ld;
+    a.K1 = K1; a.K2 = K2; a.J1 = J1; a.J2 = J2;
+    a.k1pad = tail_k1pad(DT_BF16, K1);
+    a.k2pad = (K2 + ks - 1) / ks * ks;
+    a.nblk = nblk; a.Pvec = R; a.Qvec = Q; a.alpha = alpha; a.done = done; a.partials = partials;
+    a.nbg = tail_nb(DT_BF16, DT_BF16, K1, J1, J2);
+    if (variant == 1 && tail_lds_nb(DT_BF16, DT_BF16, K1, J1, J2, 2 * a.nbg) <= 64 * 1024) a.nbg *= 2;
+    if (a.k1pad > M1.ld || a.k2pad > M2.ld) return hipErrorInvalidValue;
+    const size_t lds = tail_lds_nb(DT_BF16, DT_BF16, K1, J1, J2, a.nbg);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
+    const int grid = grid_for(ngroups, kMaxGrid);  // one partial per workgroup
+    const int j2t = (J2 + 15) / 16;
+    hipError_t e = hipErrorInvalidValue;
+    {
+        ProfScope ps("tail_r.bf16", s);
+#define CTA_TAIL_R_GO(N)                                                                {                                                                                   auto kern = k_tail_r<N>;                                                        e = ensure_lds(kern, lds);                                                      if (e == hipSuccess) {                                                              kern<<<grid, CTA_WG, lds, s>>>(a);                                              e = hipGetLastError();                                                      }                                                                           }
+        if (j2t <= 2) CTA_TAIL_R_GO(2)
+        else if (j2t <= 4) CTA_TAIL_R_GO(4)
+        else if (j2t <= 8) CTA_TAIL_R_GO(8)
+        else if (j2t <= 16) CTA_TAIL_R_GO(16)
+#undef CTA_TAIL_R_GO
+    }
+    if (e != hipSuccess) return e;
+    return launch_finalize(partials, grid, scal, POST_RHO, nullptr, s);
+}
+
 // ------------------------------------------------------------------ contiguous
 template <typename Tin, typename Tout, typename Tc, int JT>
 __global__ __launch_bounds__(CTA_WG) void k_contig(ContigArgs a, const int* done) {

@@ -100,6 +100,13 @@ hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q
                               double* partials, CgScalars* scal, int post, double* dot_out,
                               const int* done, hipStream_t s, int variant = 0);
 
+// Preconditioner tail pass (BF16 chain) with r = r - alpha q fused: R is read
+// and written, the chain input is the new r, and <r, r> is finalized with
+// POST_RHO (convergence test of the preconditioned iteration).
+hipError_t launch_tail_r(void* R, const void* Q, void* Y, const Mat& M1, const Mat& M2, int64_t nblk, int K1,
+                         int K2, int J1, int J2, const double* alpha, const int* done, double* partials,
+                         CgScalars* scal, hipStream_t s, int variant = 0);
+
 // ---- band-aware normal operator (F64 or F32; half-bandwidth w <= 4) ----
 // Y = X x_k G on the (lead, K, trail) view with gb[j * (2w+1) + d + w] = G[j][j+d].
 hipError_t launch_band_mode(int dt, const void* X, void* Y, const void* gb, int w, int64_t lead, int K,

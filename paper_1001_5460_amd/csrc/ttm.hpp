@@ -96,6 +96,11 @@ struct TailArgs {
     const int* done;
     void* Xsol;
     const double* alpha;
+    // fused residual update (preconditioned CG): the chain input is
+    // r = r - alpha q, written back to Pvec (r) with q = Qvec, and the FP64
+    // partial sums of <r, r> go to partials[blockIdx.x]
+    const void* Qvec;
+    double* partials;
 };
 
 struct ContigArgs {
@@ -1087,9 +1092,9 @@ __host__ __device__ inline int tail_zt_elems(int k1pad, int J2, int tc_size) {
     return ((J2 + 15) / 16) * 16 * (k1pad + 16 / tc_size);
 }
 
-template <typename Tin, typename Tout, typename Tc, int J2T, bool FUSE_P>
+template <typename Tin, typename Tout, typename Tc, int J2T, bool FUSE_P, bool FUSE_R = false>
 __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int nb, int nbmax,
-                                           unsigned char* smem) {
+                                           unsigned char* smem, double* dot_acc = nullptr) {
     typedef MT<Tc> T;
     constexpr int VEC = T::VEC;
     const int ldz = a.k1pad + 16 / (int)sizeof(Tc);
@@ -1107,13 +1112,14 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
         beta = cvt<Tin>(*a.beta);
         if (a.Xsol) alpha = cvt<Tin>(*a.alpha);
     }
+    if constexpr (FUSE_R) alpha = cvt<Tin>(*a.alpha);
     const int nj2t = (a.J2 + 15) / 16;
     const int ni1t = a.k1pad / 16;
     const int nks2 = a.k2pad / T::KSTEP;
     const bool aligned2 = (a.K2 % VEC) == 0;
 
     // ---- step 1: Zt[b][j2][i1] = sum_k2 X_b[i1][k2] M2[j2][k2] ----
-    if (!FUSE_P && nks2 == 1) {
+    if (!FUSE_P && !FUSE_R && nks2 == 1) {
         // one k step: the M2 fragments are the same for every tile, and a wave
         // loads the X fragments of TB tiles before the first MFMA, so TB loads
         // are in flight together (tiles past the end load the last tile again
@@ -1167,7 +1173,7 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
         typename T::acc acc[J2T];
 #pragma unroll
         for (int x = 0; x < J2T; ++x) acc[x] = T::zero();
-        if constexpr (!FUSE_P) {
+        if constexpr (!FUSE_P && !FUSE_R) {
             // X and M2 fragments of the next k step are loaded while the
             // current one multiplies (j2 tiles past nj2t read the last valid
             // one and are not used)
@@ -1202,7 +1208,39 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
             const int k2 = ks * T::KSTEP + VEC * g;
             const int nv = (i1 < a.K1) ? max(0, min(VEC, a.K2 - k2)) : 0;
             typename T::frag xf = T::zfrag();
-            {
+            if constexpr (FUSE_R) {
+                // r = r - alpha q on the fly, written back once, and its square
+                // summed in FP64
+                Tin* __restrict__ Rv = reinterpret_cast<Tin*>(a.Pvec) + off0;
+                const Tin* __restrict__ Qv = reinterpret_cast<const Tin*>(a.Qvec) + off0;
+                const int64_t off = (int64_t)i1 * a.K2 + k2;
+                constexpr int LV = 16 / sizeof(Tin);
+                if (nv == VEC && aligned2 && (VEC % LV) == 0) {
+                    typedef Tin __attribute__((ext_vector_type(LV))) vin;
+#pragma unroll
+                    for (int h = 0; h < VEC / LV; ++h) {
+                        const vin rv = *reinterpret_cast<const vin*>(Rv + off + h * LV);
+                        const vin qv = *reinterpret_cast<const vin*>(Qv + off + h * LV);
+                        const vin rn = rv - alpha * qv;
+                        *reinterpret_cast<vin*>(Rv + off + h * LV) = rn;
+#pragma unroll
+                        for (int v = 0; v < LV; ++v) {
+                            xf[h * LV + v] = cvt<Tc>(rn[v]);
+                            *dot_acc += (double)rn[v] * (double)rn[v];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        if (v < nv) {
+                            const Tin rn = Rv[off + v] - alpha * Qv[off + v];
+                            Rv[off + v] = rn;
+                            xf[v] = cvt<Tc>(rn);
+                            *dot_acc += (double)rn * (double)rn;
+                        }
+                    }
+                }
+            } else {
                 // x += alpha p (previous step, optional), then p = r + beta * p on
                 // the fly; the new p is written back once
                 Tin* __restrict__ Pv = reinterpret_cast<Tin*>(a.Pvec) + off0;
