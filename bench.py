@@ -429,7 +429,10 @@ def main():
     if not args.no_precond:
         # tensor-inverse preconditioner: strength autotuned by timing one solve per
         # candidate (outside the timed region), then the same K steps timed
-        cands = [f * p.lam for f in (16.0, 64.0, 256.0)]
+        # strengths c = lambda * 32 * 2^(i/4): a quarter-octave grid over 32..512
+        # lambda (the iteration count has a sharp minimum in c)
+        cand_f = [round(32.0 * 2.0 ** (i / 4.0), 2) for i in range(17)]
+        cands = [f * p.lam for f in cand_f]
         popts = dict(precision=args.precision, rtol=1e-8, inner_rtol=args.pc_inner_rtol,
                      max_iter=args.max_inner, max_refine=80, check_every=16)
         t = time.perf_counter()
@@ -447,7 +450,7 @@ def main():
         pinfos = [pstep() for _ in range(args.steps)]
         torch.cuda.synchronize()
         pel = time.perf_counter() - t0p
-        pre = {"c": best_c, "c_over_lambda": best_c / p.lam, "candidates_over_lambda": [16, 64, 256],
+        pre = {"c": best_c, "c_over_lambda": best_c / p.lam, "candidates_over_lambda": cand_f,
                "tuning_s": round(tune_pc_s, 3), "inner_rtol": args.pc_inner_rtol,
                "time_to_1e-8_s": round(pel / args.steps, 4),
                "iters_per_solve": sum(i["iters"] for i in pinfos) / args.steps,
