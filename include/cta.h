@@ -162,7 +162,10 @@ cta_status cta_apply_normal_op(cta_op op, const void* P, void* Q, cta_dtype dtyp
  * in the handle for later applies and solves.  Synchronous. */
 cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
 /* The variants chosen for `chain` (tail, middle, last pass) into host_variants3;
- * cta_op_set_tuning sets them: tail and middle 0 or 1 (tile shape), last
+ * cta_op_set_tuning sets them: tail 0 or 1 (tile shape), middle 0 or 1 (tile
+ * shape) or 2 (persistent workgroups with the factor in LDS that load the next
+ * 64-column tile while computing the current one, BF16 chains with
+ * n_k <= 128 and the trailing extent a multiple of 64, else as 1), last
  * 0..5 (0, 1: tile shape; 2, 3: the narrow shape with its tiles walked
  * along the second mode first, in groups of 8 planes or all planes; 4: row
  * blocks of 32 with the whole stencil staged on chip, F32/BF16 chains of

@@ -985,16 +985,23 @@ extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void
     CTA_HIP(hipEventCreate(&e1));
     int best[3] = {0, 0, 0};
     float best_ms = 1e30f;
-    // tail and middle passes: 2 tile shapes each; last pass: 6 (two tile
-    // shapes, two plane-grouped tile orders of the narrow one, row blocks with
-    // the whole stencil in LDS, and the persistent pipelined form)
-    for (int combo = 0; combo < 24; ++combo) {
-        op->var_tail[tc] = combo & 1;
-        op->var_mid[tc] = (combo >> 1) & 1;
-        op->var_last[tc] = combo >> 2;
+    // the dense passes are what is tuned: banded applies are off meanwhile
+    const bool use_band = op->use_band;
+    op->use_band = false;
+    // tail pass: 2 tile shapes; middle passes: 2 tile shapes and the
+    // persistent pipelined form; last pass: 6 (two tile shapes, two
+    // plane-grouped tile orders of the narrow one, row blocks with the whole
+    // stencil in LDS, and the persistent pipelined form)
+    for (int combo = 0; combo < 36; ++combo) {
+        op->var_tail[tc] = combo % 2;
+        op->var_mid[tc] = (combo / 2) % 3;
+        op->var_last[tc] = combo / 6;
         void* out = combo == 0 ? op->vaux : op->vq;
         cta_status st = apply_normal(op, op->vp, out, chain, POST_NONE, nullptr, false, s);
-        if (st != CTA_OK) return st;
+        if (st != CTA_OK) {
+            op->use_band = use_band;
+            return st;
+        }
         if (combo != 0) {
             CTA_HIP(launch_residual(tv, tv, op->vaux, op->vq, op->vx, op->N, op->partials, op->scal,
                                     &op->scal->dot, s));
@@ -1004,7 +1011,11 @@ extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void
         std::vector<float> ms;
         for (int r = 0; r < reps; ++r) {
             CTA_HIP(hipEventRecord(e0, s));
-            CTA_TRY(apply_normal(op, op->vp, op->vq, chain, POST_NONE, nullptr, false, s));
+            st = apply_normal(op, op->vp, op->vq, chain, POST_NONE, nullptr, false, s);
+            if (st != CTA_OK) {
+                op->use_band = use_band;
+                return st;
+            }
             CTA_HIP(hipEventRecord(e1, s));
             CTA_HIP(hipEventSynchronize(e1));
             float t = 0;
@@ -1015,11 +1026,12 @@ extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void
         const float med = ms[ms.size() / 2];
         if (med < best_ms) {
             best_ms = med;
-            best[0] = combo & 1;
-            best[1] = (combo >> 1) & 1;
-            best[2] = combo >> 2;
+            best[0] = combo % 2;
+            best[1] = (combo / 2) % 3;
+            best[2] = combo / 6;
         }
     }
+    op->use_band = use_band;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     op->var_tail[tc] = best[0];
@@ -1040,8 +1052,8 @@ extern "C" cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* hos
 extern "C" cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3) {
     if (!op || !host_variants3) return fail(CTA_ERR_ARG, "NULL argument");
     for (int i = 0; i < 3; ++i)
-        if (host_variants3[i] < 0 || host_variants3[i] > (i == 2 ? 5 : 1))
-            return fail(CTA_ERR_ARG, "variants must be 0 or 1 (tail, middle) and 0..5 (last)");
+        if (host_variants3[i] < 0 || host_variants3[i] > (i == 2 ? 5 : i == 1 ? 2 : 1))
+            return fail(CTA_ERR_ARG, "variants must be 0 or 1 (tail), 0..2 (middle) and 0..5 (last)");
     const int tc = prec_tc(chain);
     op->var_tail[tc] = host_variants3[0];
     op->var_mid[tc] = host_variants3[1];

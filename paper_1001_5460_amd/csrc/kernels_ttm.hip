@@ -1,6 +1,7 @@
 // gfx950 kernels and launchers of the mode-product passes and of the
 // normal-operator pass (see ttm.hpp for the tiling).
 #include <algorithm>
+#include <type_traits>
 
 #include "launch.hpp"
 #include "prof.hpp"
@@ -16,6 +17,17 @@ template <> struct DType<DT_BF16> { typedef bf16 T; };
 
 static int grid_for(int64_t units, int cap) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(units, cap));
+}
+
+static int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+    }
+    return cus;
 }
 
 // Raise the dynamic-LDS limit of a kernel once when it needs more than 64 KiB.
@@ -47,6 +59,129 @@ static hipError_t go_strided(StridedArgs a, const int* done, hipStream_t s) {
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
     kern<<<grid_for(a.ntiles, 65536), CTA_WG, lds, s>>>(a, done);
+    return hipGetLastError();
+}
+
+// Persistent, pipelined strided pass (BF16, K, J <= 128, trail % 64 == 0):
+// the factor is staged in LDS once per workgroup, and the next 64-column X tile
+// is loaded into registers while the current one multiplies from LDS, so the
+// only vector-memory loads of a tile are its successor's.  Same sums, in the
+// same order, as strided_tile with JT = 2, WJ = 4, CT = 4.
+constexpr int SPIPE_TN = 64;
+constexpr int SPIPE_LD = 128 + 8;   // LDS pitch (bf16) of the factor rows and X columns
+
+__device__ __forceinline__ void spipe_load(const StridedArgs& a, int64_t tile, bf16x8 (&r)[4]) {
+    const bf16* __restrict__ X = reinterpret_cast<const bf16*>(a.X);
+    const int64_t b = tile / a.ntt;
+    const int64_t t0 = (tile - b * a.ntt) * SPIPE_TN;
+    const bf16* xb = X + b * (int64_t)a.K * a.trail + t0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int u = threadIdx.x + CTA_WG * i;
+        const int cg = u & 7, kp = u >> 3;   // column group of 8, row pair
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = 2 * kp + h;
+            bf16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (bf16)0.f;
+            if (k < a.K) v = *reinterpret_cast<const bf16x8*>(xb + (int64_t)k * a.trail + cg * 8);
+            r[2 * i + h] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const int* done) {
+    if (done && *done) return;
+    typedef MT<bf16> T;
+    constexpr int JT = 2, CT = 4, VEC = T::VEC;
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16* Ms = reinterpret_cast<bf16*>(smem);                 // [128][SPIPE_LD]
+    bf16* Xs = Ms + 128 * SPIPE_LD;                            // [64][SPIPE_LD]
+    const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
+    // the factor, zero outside J x K
+    for (int u = threadIdx.x; u < 128 * 16; u += CTA_WG) {
+        const int j = u >> 4, c8 = (u & 15) * 8;
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (bf16)0.f;
+        if (j < a.J && c8 < a.kpad) v = *reinterpret_cast<const bf16x8*>(M + (int64_t)j * a.ldm + c8);
+        *reinterpret_cast<bf16x8*>(Ms + j * SPIPE_LD + c8) = v;
+    }
+    const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
+    bf16x8 r[4];
+    if (first < a.ntiles) spipe_load(a, first, r);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, l16 = lane & 15;
+    const int jb = wave * JT * 16;
+    bf16* __restrict__ Y = reinterpret_cast<bf16*>(a.Y);
+    for (int64_t tile = first; tile < a.ntiles; tile += step) {
+        // registers -> Xs[t][k]
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int u = threadIdx.x + CTA_WG * i;
+            const int cg = u & 7, kp = u >> 3;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                typedef bf16 __attribute__((ext_vector_type(2))) bf16x2;
+                bf16x2 pr;
+                pr[0] = r[2 * i][c];
+                pr[1] = r[2 * i + 1][c];
+                *reinterpret_cast<bf16x2*>(Xs + (cg * 8 + c) * SPIPE_LD + 2 * kp) = pr;
+            }
+        }
+        __syncthreads();
+        if (tile + step < a.ntiles) spipe_load(a, tile + step, r);
+        typename T::acc acc[JT][CT];
+#pragma unroll
+        for (int x = 0; x < JT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
+        const int nks = a.kpad / T::KSTEP;
+        for (int ks = 0; ks < nks; ++ks) {
+            const int k0 = ks * T::KSTEP + VEC * g;
+            typename T::frag xa[CT], mb[JT];
+#pragma unroll
+            for (int y = 0; y < CT; ++y)
+                xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (y * 16 + l16) * SPIPE_LD + k0);
+#pragma unroll
+            for (int x = 0; x < JT; ++x)
+                mb[x] = *reinterpret_cast<const typename T::frag*>(Ms + (jb + x * 16 + l16) * SPIPE_LD + k0);
+#pragma unroll
+            for (int x = 0; x < JT; ++x)
+#pragma unroll
+                for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
+        }
+        const int64_t b = tile / a.ntt;
+        const int64_t t0 = (tile - b * a.ntt) * SPIPE_TN;
+        bf16* yb = Y + b * (int64_t)a.J * a.trail + t0;
+#pragma unroll
+        for (int x = 0; x < JT; ++x) {
+            const int j = jb + x * 16 + l16;
+            if (j >= a.J) continue;
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+                typedef bf16 __attribute__((ext_vector_type(4))) bf16x4;
+                bf16x4 o;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) o[q] = (bf16)acc[x][y][q];
+                *reinterpret_cast<bf16x4*>(yb + (int64_t)j * a.trail + y * 16 + 4 * g) = o;
+            }
+        }
+        __syncthreads();  // Xs is rewritten by the next tile
+    }
+}
+
+static hipError_t go_strided_pipe(StridedArgs a, const int* done, hipStream_t s) {
+    if (a.kpad > 128 || a.J > 128 || a.trail % SPIPE_TN != 0) return hipErrorNotSupported;
+    a.ntt = a.trail / SPIPE_TN;
+    a.ntiles = a.lead * a.ntt;
+    const size_t lds = (size_t)(128 + SPIPE_TN) * SPIPE_LD * sizeof(bf16);
+    hipError_t e = ensure_lds(k_strided_pipe, lds);
+    if (e != hipSuccess) return e;
+    int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);
+    grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
+    k_strided_pipe<<<grid, CTA_WG, lds, s>>>(a, done);
     return hipGetLastError();
 }
 
@@ -88,6 +223,15 @@ static bool use_flat(const StridedArgs& a) {
 template <typename Tin, typename Tout, typename Tc>
 static hipError_t strided_T(StridedArgs a, int variant, const int* done, hipStream_t s) {
     const int jt = (a.J + 15) / 16;
+    if constexpr (std::is_same<Tin, bf16>::value && std::is_same<Tout, bf16>::value &&
+                  std::is_same<Tc, bf16>::value) {
+        // variant 2: persistent pipelined pass where its shape allows, else as 1
+        if (variant == 2) {
+            const hipError_t e = go_strided_pipe(a, done, s);
+            if (e != hipErrorNotSupported) return e;
+        }
+    }
+    if (variant == 2) variant = 1;
     if (use_flat<Tin, Tc>(a)) {
         if (jt <= 1) return go_strided_flat<Tin, Tout, Tc, 1, 1, 1>(a, done, s);
         if (jt <= 2) return go_strided_flat<Tin, Tout, Tc, 1, 2, 2>(a, done, s);
@@ -193,16 +337,6 @@ __global__ __launch_bounds__(CTA_WG) __attribute__((amdgpu_waves_per_eu(3))) voi
     block_partial(dot, st.partials, red);
 }
 
-static int device_cus() {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            cus = 256;
-    }
-    return cus;
-}
 
 static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int* grid_out, const int* done,
                                hipStream_t s) {

@@ -108,17 +108,19 @@ def test_unsupported_wide_regulariser():
 @pytest.mark.parametrize("n,m", [((16, 12, 10, 8), (24, 18, 15, 12)), ((32, 32, 32), (48, 48, 48)),
                                  ((40, 24, 20, 16), (60, 36, 30, 24)),
                                  ((72, 32, 24, 16), (108, 48, 36, 24)),
-                                 ((112, 16, 12, 8), (168, 24, 18, 12))])
+                                 ((112, 16, 12, 8), (168, 24, 18, 12)),
+                                 ((20, 100, 16, 8), (30, 150, 24, 12))])
 def test_tile_variants_match_oracle(n, m, chain):
     torch = torch_cuda()
     p, ref_op = _op(n, m, 1e-3)
     op = cta.Operator(p.A, p.D, p.lam)
+    op.set_banded(False)   # the dense passes are the ones with tile variants
     dt = torch.float64 if chain == "f64" else torch.float32
     P = dev(np.random.default_rng(11).standard_normal(n), dt)
     ref = ref_op(host(P))
     outs = []
-    for combo in range(24):
-        cta.cta_op_set_tuning(op.handle, chain, combo & 1, (combo >> 1) & 1, combo >> 2)
+    for combo in range(36):
+        cta.cta_op_set_tuning(op.handle, chain, combo % 2, (combo // 2) % 3, combo // 6)
         Q = op.apply(P, chain=chain)
         torch.cuda.synchronize()
         assert rel_fro(host(Q), ref) <= TOL[chain]
