@@ -72,9 +72,9 @@ constexpr int SPIPE_LD = 128 + 8;   // LDS pitch (bf16) of the factor rows and X
 
 __device__ __forceinline__ void spipe_load(const StridedArgs& a, int64_t tile, bf16x8 (&r)[4]) {
     const bf16* __restrict__ X = reinterpret_cast<const bf16*>(a.X);
-    const int64_t b = tile / a.ntt;
-    const int64_t t0 = (tile - b * a.ntt) * SPIPE_TN;
-    const bf16* xb = X + b * (int64_t)a.K * a.trail + t0;
+    const int b = fast_div((int)tile, a.tmul, a.tshift);  // tile / ntt
+    const int64_t t0 = (tile - (int64_t)b * a.ntt) * SPIPE_TN;
+    const bf16* xb = X + (int64_t)b * a.K * a.trail + t0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int u = threadIdx.x + CTA_WG * i;
@@ -152,9 +152,9 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
 #pragma unroll
                 for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
         }
-        const int64_t b = tile / a.ntt;
-        const int64_t t0 = (tile - b * a.ntt) * SPIPE_TN;
-        bf16* yb = Y + b * (int64_t)a.J * a.trail + t0;
+        const int b = fast_div((int)tile, a.tmul, a.tshift);
+        const int64_t t0 = (tile - (int64_t)b * a.ntt) * SPIPE_TN;
+        bf16* yb = Y + (int64_t)b * a.J * a.trail + t0;
 #pragma unroll
         for (int x = 0; x < JT; ++x) {
             const int j = jb + x * 16 + l16;
@@ -176,6 +176,8 @@ static hipError_t go_strided_pipe(StridedArgs a, const int* done, hipStream_t s)
     if (a.kpad > 128 || a.J > 128 || a.trail % SPIPE_TN != 0) return hipErrorNotSupported;
     a.ntt = a.trail / SPIPE_TN;
     a.ntiles = a.lead * a.ntt;
+    if (a.ntiles >= ((int64_t)1 << 30)) return hipErrorNotSupported;
+    fastdiv_init((uint32_t)a.ntt, &a.tmul, &a.tshift);
     const size_t lds = (size_t)(128 + SPIPE_TN) * SPIPE_LD * sizeof(bf16);
     hipError_t e = ensure_lds(k_strided_pipe, lds);
     if (e != hipSuccess) return e;
@@ -342,7 +344,8 @@ static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int*
                                hipStream_t s) {
     const int N = st.order;
     const int nN = (int)st.ext[N - 1];
-    if (a.kpad != 128 || a.K != a.J || a.trail % PIPE_TN != 0 || nN % 4 != 0 || a.trail >= (int64_t(1) << 30))
+    if (a.kpad != 128 || a.K != a.J || a.trail % PIPE_TN != 0 || nN % 4 != 0 ||
+        a.trail / PIPE_TN >= (int64_t(1) << 22))   // tile columns from float reciprocals
         return hipErrorNotSupported;
     a.ntt = a.trail / PIPE_TN;
     a.ntiles = a.ntt;

@@ -45,6 +45,16 @@ __device__ __forceinline__ int fast_div(int n, uint32_t mul, int shift) {
     return (int)((__umulhi(mul, (uint32_t)n) + (uint32_t)n) >> shift);
 }
 
+// floor(n / d) for 0 <= n < 2^22 and d >= 1, with inv = 1.0f / d: the float
+// quotient is within one of the exact one, and one correction step fixes it
+// (a few instructions instead of an integer division)
+__device__ __forceinline__ int small_div(int n, int d, float inv) {
+    int q = (int)((float)n * inv);
+    const int r = n - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
+}
+
 struct StridedArgs {
     const void* X;
     void* Y;
@@ -756,8 +766,20 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
         for (int u = threadIdx.x; u < K * 5; u += CTA_WG) band1[u] = st.rband[0][u];
     if (hasN)
         for (int u = threadIdx.x; u < nN * 5; u += CTA_WG) bandN[u] = st.rband[N - 1][u];
+    // first column of a tile (last_tile_col) with 32-bit quotients from float
+    // reciprocals: the tile count is below 2^22 (checked by the launcher)
+    const int cpp = (int)(a.plane / TN), per = cpp * a.pgroup;
+    const float inv_per = a.pgroup > 0 ? 1.0f / (float)per : 0.f;
+    const float inv_pg = a.pgroup > 0 ? 1.0f / (float)a.pgroup : 0.f;
+    auto tcol = [&](int64_t tl) -> int {
+        const int t = (int)tl;
+        if (a.pgroup <= 0) return t * TN;
+        const int grp = small_div(t, per, inv_per), rr = t - grp * per;
+        const int c = small_div(rr, a.pgroup, inv_pg), ig = rr - c * a.pgroup;
+        return (grp * a.pgroup + ig) * (int)a.plane + c * TN;
+    };
     PipeRegs r;
-    if (first < a.ntiles) pipe_load<KPAD>(a, P, (int)last_tile_col<TN>(a, first), K, r);
+    if (first < a.ntiles) pipe_load<KPAD>(a, P, tcol(first), K, r);
     const Tv lam = (Tv)st.lam;
     // Order of the memory traffic inside one tile.  The vector-memory counter
     // retires loads in issue order, so a load waits for every load issued
@@ -768,7 +790,7 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
     constexpr int IPT = KPAD * GPR / CTA_WG;    // items per thread (rows <= KPAD)
     const int nitem = a.J * GPR;
     for (int64_t tile = first; tile < a.ntiles; tile += step) {
-        const int t0 = (int)last_tile_col<TN>(a, tile);
+        const int t0 = tcol(tile);
         pipe_store<KPAD>(r, Xs, Pw, K);
         __syncthreads();
         // ---- middle-mode regulariser taps of this tile's items ----
@@ -818,7 +840,7 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
 #pragma unroll
                 for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
             mfma_cols<bf16, JT, CT>(Xs, ldx, M, a.ldm, 0, jb, KPAD, acc);
-            if (tile + step < a.ntiles) pipe_load<KPAD>(a, P, (int)last_tile_col<TN>(a, tile + step), K, r);
+            if (tile + step < a.ntiles) pipe_load<KPAD>(a, P, tcol(tile + step), K, r);
             __syncthreads();  // Xs is dead; its space becomes Qs
 #pragma unroll
             for (int x = 0; x < JT; ++x) {
@@ -1116,6 +1138,8 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
     const int nj2t = (a.J2 + 15) / 16;
     const int ni1t = a.k1pad / 16;
     const int nks2 = a.k2pad / T::KSTEP;
+    // tile indices are split with a float reciprocal (small_div), not integer division
+    const float inv_ni1t = 1.0f / (float)ni1t, inv_nj2t = 1.0f / (float)nj2t;
     const bool aligned2 = (a.K2 % VEC) == 0;
 
     // ---- step 1: Zt[b][j2][i1] = sum_k2 X_b[i1][k2] M2[j2][k2] ----
@@ -1137,7 +1161,7 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
 #pragma unroll
             for (int i = 0; i < TB; ++i) {
                 const int it = min(it0 + i * CTA_WAVES, ntile - 1);
-                const int bl = it / ni1t, ti = it - bl * ni1t;
+                const int bl = small_div(it, ni1t, inv_ni1t), ti = it - bl * ni1t;
                 const int i1 = ti * 16 + l16;
                 const Tin* __restrict__ X = reinterpret_cast<const Tin*>(a.X) + (blk0 + bl) * bin;
                 const int nv = (i1 < a.K1) ? max(0, min(VEC, a.K2 - k2)) : 0;
@@ -1151,7 +1175,7 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
                 for (int x = 0; x < J2T; ++x)
                     acc[x] = x < nj2t ? T::mma(xf[i], mf[x], T::zero()) : T::zero();
                 if (it >= ntile) continue;
-                const int bl = it / ni1t, ti = it - bl * ni1t;
+                const int bl = small_div(it, ni1t, inv_ni1t), ti = it - bl * ni1t;
                 Tc* Zb = Zt + bl * zsz;
 #pragma unroll
                 for (int x = 0; x < J2T; ++x) {
@@ -1166,7 +1190,7 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
         }
     } else
     for (int it = wave; it < nb * ni1t; it += CTA_WAVES) {
-        const int bl = it / ni1t, ti = it - bl * ni1t;
+        const int bl = small_div(it, ni1t, inv_ni1t), ti = it - bl * ni1t;
         const int64_t off0 = (blk0 + bl) * bin;
         const Tin* __restrict__ X = reinterpret_cast<const Tin*>(a.X) + off0;
         const int i1 = ti * 16 + l16;
@@ -1300,10 +1324,11 @@ __device__ __forceinline__ void tail_group(const TailArgs& a, int64_t blk0, int 
     // ---- step 2: Ys[b][j1][j2] = sum_i1 M1[j1][i1] Zt[b][j2][i1] ----
     const int nj1t = (a.J1 + 15) / 16;
     const int nsub = nj2t * nj1t;
+    const float inv_nsub = 1.0f / (float)nsub;
     const int nks1 = a.k1pad / T::KSTEP;
     for (int sidx = wave; sidx < nb * nsub; sidx += CTA_WAVES) {
-        const int bl = sidx / nsub, sb = sidx - bl * nsub;
-        const int x2 = sb % nj2t, x1 = sb / nj2t;
+        const int bl = small_div(sidx, nsub, inv_nsub), sb = sidx - bl * nsub;
+        const int x1 = small_div(sb, nj2t, inv_nj2t), x2 = sb - x1 * nj2t;
         const Tc* Zb = Zt + bl * zsz;
         typename T::acc acc = T::zero();
         // the M1 fragment of the next k step is loaded during the current MFMA
