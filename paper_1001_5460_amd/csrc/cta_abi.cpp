@@ -251,9 +251,14 @@ cta_status apply_precond(cta_op_s* op, const void* R, void* Z, int prec, int pos
         stride *= op->n[k];
         st.rband[k] = nullptr;
     }
-    e = launch_normal_last(tc, tv, tc, cur, Z, op->Pinv[tc][0], (int)op->n[0], (int)op->n[0],
-                           op->N / op->n[0], st, op->partials, op->scal, post, dot_out, done, s,
-                           op->var_last[tc]);
+    e = hipErrorNotSupported;
+    if (tc == DT_BF16 && tv == DT_F32)
+        e = launch_last_nr(cur, Z, R, op->Pinv[tc][0], (int)op->n[0], op->N / op->n[0], op->partials, op->scal,
+                           post, dot_out, done, s);
+    if (e == hipErrorNotSupported)
+        e = launch_normal_last(tc, tv, tc, cur, Z, op->Pinv[tc][0], (int)op->n[0], (int)op->n[0],
+                               op->N / op->n[0], st, op->partials, op->scal, post, dot_out, done, s,
+                               op->var_last[tc]);
     if (e != hipSuccess) return fail(CTA_ERR_HIP, "preconditioner last pass: %s", hipGetErrorString(e));
     return CTA_OK;
 }

@@ -507,6 +507,127 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
     return hipErrorInvalidValue;
 }
 
+// Last pass without a regulariser (the preconditioner's mode-1 pass, BF16
+// chain): Z = T x_1 M in FP32 and the FP64 partials of <R, Z>.  Persistent
+// like k_strided_pipe (M in LDS, the next 64-column tile prefetched into
+// registers); the R values a tile needs are loaded before that prefetch, so
+// their wait does not include it.
+__global__ __launch_bounds__(CTA_WG) void k_last_nr_pipe(StridedArgs a, const float* __restrict__ R,
+                                                         double* partials, const int* done) {
+    if (done && *done) return;
+    typedef MT<bf16> T;
+    constexpr int JT = 2, CT = 4, VEC = T::VEC;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[CTA_WAVES];
+    bf16* Ms = reinterpret_cast<bf16*>(smem);
+    bf16* Xs = Ms + 128 * SPIPE_LD;
+    const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
+    for (int u = threadIdx.x; u < 128 * 16; u += CTA_WG) {
+        const int j = u >> 4, c8 = (u & 15) * 8;
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (bf16)0.f;
+        if (j < a.J && c8 < a.kpad) v = *reinterpret_cast<const bf16x8*>(M + (int64_t)j * a.ldm + c8);
+        *reinterpret_cast<bf16x8*>(Ms + j * SPIPE_LD + c8) = v;
+    }
+    const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
+    bf16x8 r[4];
+    if (first < a.ntiles) spipe_load(a, first, r);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, l16 = lane & 15;
+    const int jb = wave * JT * 16;
+    float* __restrict__ Z = reinterpret_cast<float*>(a.Y);
+    double dot = 0.0;
+    for (int64_t tile = first; tile < a.ntiles; tile += step) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int u = threadIdx.x + CTA_WG * i;
+            const int cg = u & 7, kp = u >> 3;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                typedef bf16 __attribute__((ext_vector_type(2))) bf16x2;
+                bf16x2 pr;
+                pr[0] = r[2 * i][c];
+                pr[1] = r[2 * i + 1][c];
+                *reinterpret_cast<bf16x2*>(Xs + (cg * 8 + c) * SPIPE_LD + 2 * kp) = pr;
+            }
+        }
+        __syncthreads();
+        // R of this tile's outputs (rows past J read row J-1 and are not used)
+        const int64_t t0 = tile * SPIPE_TN;
+        floatx4 rv[JT][CT];
+#pragma unroll
+        for (int x = 0; x < JT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+                const int j = min(jb + x * 16 + l16, a.J - 1);
+                rv[x][y] = *reinterpret_cast<const floatx4*>(R + (int64_t)j * a.trail + t0 + y * 16 + 4 * g);
+            }
+        if (tile + step < a.ntiles) spipe_load(a, tile + step, r);
+        typename T::acc acc[JT][CT];
+#pragma unroll
+        for (int x = 0; x < JT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
+        const int nks = a.kpad / T::KSTEP;
+        for (int ks = 0; ks < nks; ++ks) {
+            const int k0 = ks * T::KSTEP + VEC * g;
+            typename T::frag xa[CT], mb[JT];
+#pragma unroll
+            for (int y = 0; y < CT; ++y)
+                xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (y * 16 + l16) * SPIPE_LD + k0);
+#pragma unroll
+            for (int x = 0; x < JT; ++x)
+                mb[x] = *reinterpret_cast<const typename T::frag*>(Ms + (jb + x * 16 + l16) * SPIPE_LD + k0);
+#pragma unroll
+            for (int x = 0; x < JT; ++x)
+#pragma unroll
+                for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
+        }
+#pragma unroll
+        for (int x = 0; x < JT; ++x) {
+            const int j = jb + x * 16 + l16;
+            if (j >= a.J) continue;
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+                *reinterpret_cast<floatx4*>(Z + (int64_t)j * a.trail + t0 + y * 16 + 4 * g) = acc[x][y];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dot += (double)rv[x][y][q] * (double)acc[x][y][q];
+            }
+        }
+        __syncthreads();  // Xs is rewritten by the next tile
+    }
+    block_partial(dot, partials, red);
+}
+
+// The preconditioner's last pass in the pipelined form when the shape allows
+// (BF16 chain, n_1 <= 128, trail % 64 == 0); hipErrorNotSupported otherwise.
+hipError_t launch_last_nr(const void* X, void* Z, const void* R, const Mat& M, int K, int64_t trail,
+                          double* partials, CgScalars* scal, int post, double* dot_out, const int* done,
+                          hipStream_t s) {
+    StridedArgs a{};
+    a.X = X; a.Y = Z; a.M = M.p; a.ldm = M.ld;
+    a.K = K; a.J = K; a.kpad = (K + dt_kstep(DT_BF16) - 1) / dt_kstep(DT_BF16) * dt_kstep(DT_BF16);
+    a.lead = 1; a.trail = trail;
+    if (a.kpad > 128 || a.kpad > M.ld || trail % SPIPE_TN != 0) return hipErrorNotSupported;
+    a.ntt = trail / SPIPE_TN;
+    a.ntiles = a.ntt;
+    if (a.ntiles >= ((int64_t)1 << 30)) return hipErrorNotSupported;
+    fastdiv_init((uint32_t)a.ntt, &a.tmul, &a.tshift);   // spipe_load: tile / ntt (= 0 here)
+    const size_t lds = (size_t)(128 + SPIPE_TN) * SPIPE_LD * sizeof(bf16);
+    hipError_t e = ensure_lds(k_last_nr_pipe, lds);
+    if (e != hipSuccess) return e;
+    int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);
+    grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
+    {
+        ProfScope ps("normal_last_nr.bf16", s);
+        k_last_nr_pipe<<<grid, CTA_WG, lds, s>>>(a, reinterpret_cast<const float*>(R), partials, done);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess || post == POST_NONE) return e;
+    return launch_finalize(partials, grid, scal, post, dot_out, s);
+}
+
 hipError_t launch_normal_last(int tmid, int tvec, int tc, const void* X, void* Q, const Mat& M,
                               int K, int J, int64_t trail, const StencilDesc& st,
                               double* partials, CgScalars* scal, int post, double* dot_out,

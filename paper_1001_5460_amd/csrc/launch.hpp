@@ -107,6 +107,12 @@ hipError_t launch_tail_r(void* R, const void* Q, void* Y, const Mat& M1, const M
                          int K2, int J1, int J2, const double* alpha, const int* done, double* partials,
                          CgScalars* scal, hipStream_t s, int variant = 0);
 
+// Last pass without regulariser (the preconditioner's), BF16 chain, pipelined:
+// Z = X x_1 M (FP32) and <R, Z>; hipErrorNotSupported when the shape does not fit.
+hipError_t launch_last_nr(const void* X, void* Z, const void* R, const Mat& M, int K, int64_t trail,
+                          double* partials, CgScalars* scal, int post, double* dot_out, const int* done,
+                          hipStream_t s);
+
 // ---- band-aware normal operator (F64 or F32; half-bandwidth w <= 4) ----
 // Y = X x_k G on the (lead, K, trail) view with gb[j * (2w+1) + d + w] = G[j][j+d].
 hipError_t launch_band_mode(int dt, const void* X, void* Y, const void* gb, int w, int64_t lead, int K,
