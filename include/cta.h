@@ -162,7 +162,10 @@ cta_status cta_apply_normal_op(cta_op op, const void* P, void* Q, cta_dtype dtyp
  * in the handle for later applies and solves.  Synchronous. */
 cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
 /* The variants chosen for `chain` (tail, middle, last pass) into host_variants3;
- * cta_op_set_tuning sets them: tail 0 or 1 (tile shape), middle 0 or 1 (tile
+ * cta_op_set_tuning sets them: tail 0 or 1 (blocks per workgroup) or 2
+ * (persistent workgroups with both factors in LDS that load the next group's
+ * vectors while computing the current one; BF16 chains inside CG with the
+ * last two extents <= 128 and <= 32, else as 0), middle 0 or 1 (tile
  * shape) or 2 (persistent workgroups with the factor in LDS that load the next
  * 64-column tile while computing the current one, BF16 chains with
  * n_k <= 128 and the trailing extent a multiple of 64, else as 1), last

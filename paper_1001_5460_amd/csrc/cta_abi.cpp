@@ -993,7 +993,7 @@ extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void
     // the dense passes are what is tuned: banded applies are off meanwhile
     const bool use_band = op->use_band;
     op->use_band = false;
-    // tail pass: 2 tile shapes; middle passes: 2 tile shapes and the
+    // tail pass: 2 block counts; middle passes: 2 tile shapes and the
     // persistent pipelined form; last pass: 6 (two tile shapes, two
     // plane-grouped tile orders of the narrow one, row blocks with the whole
     // stencil in LDS, and the persistent pipelined form)
@@ -1037,6 +1037,47 @@ extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void
         }
     }
     op->use_band = use_band;
+    if (tc == DT_BF16 && best_ms < 1e30f) {
+        // The tail pass inside CG also applies x += alpha p and p = r + beta p;
+        // its persistent pipelined form (tail variant 2) is timed against the
+        // chosen one on that fused pass, with alpha = beta = 0 so that every
+        // apply sees the same input, and must give the identical output.
+        op->var_mid[tc] = best[1];
+        op->var_last[tc] = best[2];
+        CgScalars hs{};
+        hs.rho = 1.0;
+        hs.bnorm2 = 1.0;
+        hs.done = DONE_RUNNING;
+        CTA_HIP(hipMemcpy(op->scal, &hs, sizeof hs, hipMemcpyHostToDevice));
+        CTA_HIP(launch_fill_pattern(DT_F32, op->vr, op->N, s));
+        const int cand[2] = {best[0], 2};
+        float med2[2] = {1e30f, 1e30f};
+        bool same = true;
+        for (int c = 0; c < 2; ++c) {
+            op->var_tail[tc] = cand[c];
+            CTA_TRY(apply_normal(op, nullptr, c == 0 ? op->vaux : op->vq, chain, POST_NONE, nullptr, true, s,
+                                 op->vx, nullptr));
+            if (c == 1) {
+                CTA_HIP(launch_residual(tv, tv, op->vaux, op->vq, op->vx, op->N, op->partials, op->scal,
+                                        &op->scal->dot, s));
+                CTA_TRY(read_scal(op, s));
+                same = op->hscal->dot == 0.0;
+            }
+            std::vector<float> ms;
+            for (int r = 0; r < reps; ++r) {
+                CTA_HIP(hipEventRecord(e0, s));
+                CTA_TRY(apply_normal(op, nullptr, op->vq, chain, POST_NONE, nullptr, true, s, op->vx, nullptr));
+                CTA_HIP(hipEventRecord(e1, s));
+                CTA_HIP(hipEventSynchronize(e1));
+                float t = 0;
+                CTA_HIP(hipEventElapsedTime(&t, e0, e1));
+                ms.push_back(t);
+            }
+            std::sort(ms.begin(), ms.end());
+            med2[c] = ms[ms.size() / 2];
+        }
+        if (same && med2[1] < med2[0]) best[0] = 2;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     op->var_tail[tc] = best[0];
@@ -1057,8 +1098,8 @@ extern "C" cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* hos
 extern "C" cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3) {
     if (!op || !host_variants3) return fail(CTA_ERR_ARG, "NULL argument");
     for (int i = 0; i < 3; ++i)
-        if (host_variants3[i] < 0 || host_variants3[i] > (i == 2 ? 5 : i == 1 ? 2 : 1))
-            return fail(CTA_ERR_ARG, "variants must be 0 or 1 (tail), 0..2 (middle) and 0..5 (last)");
+        if (host_variants3[i] < 0 || host_variants3[i] > (i == 2 ? 5 : 2))
+            return fail(CTA_ERR_ARG, "variants must be 0..2 (tail, middle) and 0..5 (last)");
     const int tc = prec_tc(chain);
     op->var_tail[tc] = host_variants3[0];
     op->var_mid[tc] = host_variants3[1];

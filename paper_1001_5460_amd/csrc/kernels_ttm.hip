@@ -711,6 +711,188 @@ static hipError_t tail_T(const TailArgs& a, size_t lds, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+// Persistent, pipelined fused tail pass (BF16 chain, x and p updates fused):
+// M1 and M2 are staged in LDS once per workgroup, and the r, p (and x)
+// fragments of the workgroup's next group of blocks are loaded into registers
+// right after the current group's have been consumed, so they arrive while
+// the second MFMA step and the write-back run (which touch only LDS and
+// store).  Same sums, in the same order, as tail_group.  Shapes: k1pad and
+// J1 <= 128, K2 <= 32 with K2 % 8 == 0, J2 <= 32, at most TPIPE_TPW 16-row
+// tiles per wave per group.
+constexpr int TPIPE_TPW = 3;
+
+struct TailPipeGeom {
+    int ld1, ld2, ldz, zsz, nj1t, nj2t, ni1t, bout;
+};
+
+__host__ __device__ inline TailPipeGeom tail_pipe_geom(int k1pad, int J1, int J2) {
+    TailPipeGeom g;
+    g.ld1 = k1pad + 8;
+    g.ld2 = 32 + 8;
+    g.ldz = k1pad + 8;
+    g.nj1t = (J1 + 15) / 16;
+    g.nj2t = (J2 + 15) / 16;
+    g.ni1t = k1pad / 16;
+    g.zsz = g.nj2t * 16 * g.ldz;
+    g.bout = J1 * J2;
+    return g;
+}
+
+static size_t tail_pipe_lds(const TailPipeGeom& g, int nbg) {
+    return ((size_t)g.nj1t * 16 * g.ld1 + (size_t)g.nj2t * 16 * g.ld2 + (size_t)nbg * g.zsz +
+            (size_t)nbg * g.bout) * sizeof(bf16);
+}
+
+__global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
+    if (a.done && *a.done) return;
+    typedef MT<bf16> T;
+    constexpr int VEC = T::VEC;
+    constexpr int J2T = 2;
+    typedef float __attribute__((ext_vector_type(4))) f4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const TailPipeGeom gm = tail_pipe_geom(a.k1pad, a.J1, a.J2);
+    bf16* M1s = reinterpret_cast<bf16*>(smem);
+    bf16* M2s = M1s + gm.nj1t * 16 * gm.ld1;
+    bf16* Zt = M2s + gm.nj2t * 16 * gm.ld2;
+    bf16* Ys = Zt + a.nbg * gm.zsz;
+    const bf16* __restrict__ M1 = reinterpret_cast<const bf16*>(a.M1);
+    const bf16* __restrict__ M2 = reinterpret_cast<const bf16*>(a.M2);
+    // factors into LDS (rows past the padded extents are never read)
+    for (int u = threadIdx.x; u < gm.nj1t * 16 * (a.k1pad / 8); u += CTA_WG) {
+        const int j = u / (a.k1pad / 8), c8 = (u - j * (a.k1pad / 8)) * 8;
+        *reinterpret_cast<bf16x8*>(M1s + j * gm.ld1 + c8) =
+            *reinterpret_cast<const bf16x8*>(M1 + (int64_t)j * a.ldm1 + c8);
+    }
+    for (int u = threadIdx.x; u < gm.nj2t * 16 * 4; u += CTA_WG) {
+        const int j = u >> 2, c8 = (u & 3) * 8;
+        *reinterpret_cast<bf16x8*>(M2s + j * gm.ld2 + c8) =
+            *reinterpret_cast<const bf16x8*>(M2 + (int64_t)j * a.ldm2 + c8);
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, l16 = lane & 15;
+    const int64_t bin = (int64_t)a.K1 * a.K2;
+    const float beta = (float)*a.beta;
+    const float alpha = a.Xsol ? (float)*a.alpha : 0.f;
+    const float* __restrict__ R = reinterpret_cast<const float*>(a.X);
+    float* __restrict__ Pg = reinterpret_cast<float*>(a.Pvec);
+    float* __restrict__ Xg = reinterpret_cast<float*>(a.Xsol);
+    const int k2 = VEC * g;
+    const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
+    const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
+    f4 rr[TPIPE_TPW][2], pp[TPIPE_TPW][2], xx[TPIPE_TPW][2];
+    auto fetch = [&](int64_t grp) {
+        const int64_t blk0 = grp * a.nbg;
+        const int nb = (int)std::min<int64_t>(a.nbg, a.nblk - blk0);
+#pragma unroll
+        for (int i = 0; i < TPIPE_TPW; ++i) {
+            const int it = wave + CTA_WAVES * i;
+            if (it >= nb * gm.ni1t) continue;
+            const int bl = it / gm.ni1t, ti = it - bl * gm.ni1t;
+            const int i1 = ti * 16 + l16;
+            if (i1 >= a.K1 || k2 >= a.K2) continue;
+            const int64_t off = (blk0 + bl) * bin + (int64_t)i1 * a.K2 + k2;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                rr[i][h] = *reinterpret_cast<const f4*>(R + off + 4 * h);
+                pp[i][h] = *reinterpret_cast<const f4*>(Pg + off + 4 * h);
+                if (Xg) xx[i][h] = *reinterpret_cast<const f4*>(Xg + off + 4 * h);
+            }
+        }
+    };
+    if (first < ngroups) fetch(first);
+    __syncthreads();  // factors staged
+    for (int64_t grp = first; grp < ngroups; grp += step) {
+        const int64_t blk0 = grp * a.nbg;
+        const int nb = (int)std::min<int64_t>(a.nbg, a.nblk - blk0);
+        // ---- step 1 from the fetched fragments: x += alpha p, p = r + beta p, Zt ----
+#pragma unroll
+        for (int i = 0; i < TPIPE_TPW; ++i) {
+            const int it = wave + CTA_WAVES * i;
+            if (it >= nb * gm.ni1t) continue;
+            const int bl = it / gm.ni1t, ti = it - bl * gm.ni1t;
+            const int i1 = ti * 16 + l16;
+            typename T::frag xf = T::zfrag();
+            if (i1 < a.K1 && k2 < a.K2) {
+                const int64_t off = (blk0 + bl) * bin + (int64_t)i1 * a.K2 + k2;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (Xg) *reinterpret_cast<f4*>(Xg + off + 4 * h) = xx[i][h] + alpha * pp[i][h];
+                    const f4 pn = rr[i][h] + beta * pp[i][h];
+                    *reinterpret_cast<f4*>(Pg + off + 4 * h) = pn;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) xf[4 * h + v] = (bf16)pn[v];
+                }
+            }
+            bf16* Zb = Zt + bl * gm.zsz;
+#pragma unroll
+            for (int x = 0; x < J2T; ++x) {
+                if (x < gm.nj2t) {
+                    const typename T::frag mf =
+                        *reinterpret_cast<const typename T::frag*>(M2s + (x * 16 + l16) * gm.ld2 + k2);
+                    const typename T::acc acc = T::mma(xf, mf, T::zero());
+                    const int j2 = x * 16 + l16;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Zb[j2 * gm.ldz + ti * 16 + T::arow(lane, r)] = (bf16)acc[r];
+                }
+            }
+        }
+        // the next group's fragments load while steps 2 and 3 run
+        if (grp + step < ngroups) fetch(grp + step);
+        __syncthreads();
+        // ---- step 2: Ys[b][j1][j2] = sum_i1 M1[j1][i1] Zt[b][j2][i1] ----
+        const int nsub = gm.nj2t * gm.nj1t;
+        const int nks1 = a.k1pad / T::KSTEP;
+        for (int sidx = wave; sidx < nb * nsub; sidx += CTA_WAVES) {
+            const int bl = sidx / nsub, sb = sidx - bl * nsub;
+            const int x1 = sb / gm.nj2t, x2 = sb - x1 * gm.nj2t;
+            const bf16* zrow = Zt + bl * gm.zsz + (x2 * 16 + l16) * gm.ldz + VEC * g;
+            const bf16* mrow = M1s + (x1 * 16 + l16) * gm.ld1 + VEC * g;
+            typename T::acc acc = T::zero();
+            for (int ks = 0; ks < nks1; ++ks) {
+                const typename T::frag zf = *reinterpret_cast<const typename T::frag*>(zrow + ks * T::KSTEP);
+                const typename T::frag mf = *reinterpret_cast<const typename T::frag*>(mrow + ks * T::KSTEP);
+                acc = T::mma(zf, mf, acc);
+            }
+            const int j1 = x1 * 16 + l16;
+            if (j1 < a.J1) {
+                bf16* yb = Ys + bl * gm.bout + j1 * a.J2;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j2 = x2 * 16 + T::arow(lane, r);
+                    if (j2 < a.J2) yb[j2] = (bf16)acc[r];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- step 3: contiguous write-back of the nb output blocks ----
+        bf16* __restrict__ Y = reinterpret_cast<bf16*>(a.Y) + blk0 * gm.bout;
+        const int total = nb * gm.bout;
+        if ((reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (total % 8) == 0) {
+            for (int i = threadIdx.x * 8; i < total; i += CTA_WG * 8)
+                *reinterpret_cast<bf16x8*>(Y + i) = *reinterpret_cast<const bf16x8*>(Ys + i);
+        } else {
+            for (int i = threadIdx.x; i < total; i += CTA_WG) Y[i] = Ys[i];
+        }
+        __syncthreads();  // Zt and Ys are reused by the next group
+    }
+}
+
+static hipError_t go_tail_pipe(TailArgs a, hipStream_t s) {
+    const TailPipeGeom gm = tail_pipe_geom(a.k1pad, a.J1, a.J2);
+    if (a.k1pad > 128 || a.J1 > 128 || a.k2pad > 32 || a.J2 > 32 || a.K2 % 8 != 0 ||
+        a.nbg * gm.ni1t > CTA_WAVES * TPIPE_TPW || a.k1pad > a.ldm1 || a.k2pad > a.ldm2)
+        return hipErrorNotSupported;
+    const size_t lds = tail_pipe_lds(gm, a.nbg);
+    if (lds > 64 * 1024) return hipErrorNotSupported;
+    const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
+    int grid = (int)std::min<int64_t>(ngroups, (int64_t)device_cus() * 3);
+    grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
+    hipError_t e = ensure_lds(k_tail_pipe, lds);
+    if (e != hipSuccess) return e;
+    k_tail_pipe<<<grid, CTA_WG, lds, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const Mat& M1,
                        const Mat& M2, int64_t nblk, int K1, int K2, int J1, int J2, void* Pvec,
                        const double* beta, const int* done, hipStream_t s, int variant, void* Xsol,
@@ -732,6 +914,11 @@ hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const 
     const bool fuse = Pvec != nullptr;
     ProfScope ps(fuse ? (tc == DT_F64 ? "tail_p.f64" : tc == DT_F32 ? "tail_p.f32" : "tail_p.bf16")
                       : (tc == DT_F64 ? "tail.f64" : tc == DT_F32 ? "tail.f32" : "tail.bf16"), s);
+    if (variant == 2 && fuse && tin == DT_F32 && tout == DT_BF16 && tc == DT_BF16) {
+        // persistent pipelined form where the shape allows, else as variant 0
+        const hipError_t e = go_tail_pipe(a, s);
+        if (e != hipErrorNotSupported) return e;
+    }
     if (tin == DT_F32 && tout == DT_BF16 && tc == DT_BF16)
         return fuse ? tail_T<float, bf16, bf16, true>(a, lds, s)
                     : tail_T<float, bf16, bf16, false>(a, lds, s);

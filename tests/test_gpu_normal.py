@@ -119,8 +119,8 @@ def test_tile_variants_match_oracle(n, m, chain):
     P = dev(np.random.default_rng(11).standard_normal(n), dt)
     ref = ref_op(host(P))
     outs = []
-    for combo in range(36):
-        cta.cta_op_set_tuning(op.handle, chain, combo % 2, (combo // 2) % 3, combo // 6)
+    for combo in range(54):   # tail 2 applies to the fused tail only; here it is tail 0
+        cta.cta_op_set_tuning(op.handle, chain, combo % 3, (combo // 3) % 3, combo // 9)
         Q = op.apply(P, chain=chain)
         torch.cuda.synchronize()
         assert rel_fro(host(Q), ref) <= TOL[chain]
@@ -131,3 +131,22 @@ def test_tile_variants_match_oracle(n, m, chain):
     assert set(picked) == {"tail", "middle", "last"}
     Q = op.apply(P, chain=chain)
     assert torch.equal(Q, outs[0])
+
+
+@pytest.mark.parametrize("n,m", [((20, 16, 96, 24), (30, 24, 144, 36)),   # two blocks per group
+                                 ((16, 12, 40, 24), (24, 18, 60, 36)),    # one block, padded K1
+                                 ((10, 8, 33, 16), (15, 12, 50, 24))])    # ragged K1
+def test_pipelined_fused_tail_matches_plain_tail(n, m):
+    """The fused tail pass (x and p updates inside CG) in its pipelined form
+    (tail variant 2) gives bit-identical iterates to the plain form."""
+    torch = torch_cuda()
+    p, _ = _op(n, m, 1e-3)
+    op = cta.Operator(p.A, p.D, p.lam)
+    B = dev(np.random.default_rng(13).standard_normal(n), torch.float32)
+    out = []
+    for tail in (0, 2):
+        cta.cta_op_set_tuning(op.handle, "bf16", tail, 0, 0)
+        X, info = op.solve(B, precision="bf16", rtol=1e-30, max_iter=15, check_every=15)
+        assert info["iters"] == 15
+        out.append(X.clone())
+    assert torch.equal(out[0], out[1])
