@@ -743,6 +743,9 @@ static size_t tail_pipe_lds(const TailPipeGeom& g, int nbg) {
             (size_t)nbg * g.bout) * sizeof(bf16);
 }
 
+// FR: the preconditioner's form, r = r - alpha q (R = Pvec, q = Qvec) with the
+// FP64 partials of <r, r>, instead of the x and p updates.
+template <bool FR>
 __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
     if (a.done && *a.done) return;
     typedef MT<bf16> T;
@@ -771,11 +774,15 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int64_t bin = (int64_t)a.K1 * a.K2;
-    const float beta = (float)*a.beta;
-    const float alpha = a.Xsol ? (float)*a.alpha : 0.f;
-    const float* __restrict__ R = reinterpret_cast<const float*>(a.X);
-    float* __restrict__ Pg = reinterpret_cast<float*>(a.Pvec);
-    float* __restrict__ Xg = reinterpret_cast<float*>(a.Xsol);
+    const float beta = FR ? 0.f : (float)*a.beta;
+    const float alpha = (FR || a.Xsol) ? (float)*a.alpha : 0.f;
+    // FR: rr = r (read from and written to Pvec), pp = q
+    const float* __restrict__ R = reinterpret_cast<const float*>(FR ? a.Pvec : a.X);
+    float* __restrict__ Pg = reinterpret_cast<float*>(FR ? const_cast<void*>(a.Qvec) : a.Pvec);
+    float* __restrict__ Xg = FR ? nullptr : reinterpret_cast<float*>(a.Xsol);
+    float* __restrict__ Rw = reinterpret_cast<float*>(a.Pvec);
+    __shared__ double red[CTA_WAVES];
+    double dot = 0.0;
     const int k2 = VEC * g;
     const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
     const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
@@ -816,11 +823,21 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
                 const int64_t off = (blk0 + bl) * bin + (int64_t)i1 * a.K2 + k2;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    if (Xg) *reinterpret_cast<f4*>(Xg + off + 4 * h) = xx[i][h] + alpha * pp[i][h];
-                    const f4 pn = rr[i][h] + beta * pp[i][h];
-                    *reinterpret_cast<f4*>(Pg + off + 4 * h) = pn;
+                    if constexpr (FR) {
+                        const f4 rn = rr[i][h] - alpha * pp[i][h];
+                        *reinterpret_cast<f4*>(Rw + off + 4 * h) = rn;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) xf[4 * h + v] = (bf16)pn[v];
+                        for (int v = 0; v < 4; ++v) {
+                            xf[4 * h + v] = (bf16)rn[v];
+                            dot += (double)rn[v] * (double)rn[v];
+                        }
+                    } else {
+                        if (Xg) *reinterpret_cast<f4*>(Xg + off + 4 * h) = xx[i][h] + alpha * pp[i][h];
+                        const f4 pn = rr[i][h] + beta * pp[i][h];
+                        *reinterpret_cast<f4*>(Pg + off + 4 * h) = pn;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) xf[4 * h + v] = (bf16)pn[v];
+                    }
                 }
             }
             bf16* Zb = Zt + bl * gm.zsz;
@@ -875,9 +892,11 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
         }
         __syncthreads();  // Zt and Ys are reused by the next group
     }
+    if constexpr (FR) block_partial(dot, a.partials, red);
 }
 
-static hipError_t go_tail_pipe(TailArgs a, hipStream_t s) {
+template <bool FR>
+static hipError_t go_tail_pipe(TailArgs a, hipStream_t s, int* grid_out = nullptr) {
     const TailPipeGeom gm = tail_pipe_geom(a.k1pad, a.J1, a.J2);
     if (a.k1pad > 128 || a.J1 > 128 || a.k2pad > 32 || a.J2 > 32 || a.K2 % 8 != 0 ||
         a.nbg * gm.ni1t > CTA_WAVES * TPIPE_TPW || a.k1pad > a.ldm1 || a.k2pad > a.ldm2)
@@ -887,9 +906,10 @@ static hipError_t go_tail_pipe(TailArgs a, hipStream_t s) {
     const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
     int grid = (int)std::min<int64_t>(ngroups, (int64_t)device_cus() * 3);
     grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
-    hipError_t e = ensure_lds(k_tail_pipe, lds);
+    hipError_t e = ensure_lds(k_tail_pipe<FR>, lds);
     if (e != hipSuccess) return e;
-    k_tail_pipe<<<grid, CTA_WG, lds, s>>>(a);
+    if (grid_out) *grid_out = grid;
+    k_tail_pipe<FR><<<grid, CTA_WG, lds, s>>>(a);
     return hipGetLastError();
 }
 
@@ -916,7 +936,7 @@ hipError_t launch_tail(int tin, int tout, int tc, const void* X, void* Y, const 
                       : (tc == DT_F64 ? "tail.f64" : tc == DT_F32 ? "tail.f32" : "tail.bf16"), s);
     if (variant == 2 && fuse && tin == DT_F32 && tout == DT_BF16 && tc == DT_BF16) {
         // persistent pipelined form where the shape allows, else as variant 0
-        const hipError_t e = go_tail_pipe(a, s);
+        const hipError_t e = go_tail_pipe<false>(a, s);
         if (e != hipErrorNotSupported) return e;
     }
     if (tin == DT_F32 && tout == DT_BF16 && tc == DT_BF16)
@@ -968,17 +988,29 @@ hipError_t launch_tail_r(void* R, const void* Q, void* Y, const Mat& M1, const M
     const size_t lds = tail_lds_nb(DT_BF16, DT_BF16, K1, J1, J2, a.nbg);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
-    const int grid = grid_for(ngroups, kMaxGrid);  // one partial per workgroup
+    int grid = grid_for(ngroups, kMaxGrid);  // one partial per workgroup
     const int j2t = (J2 + 15) / 16;
     hipError_t e = hipErrorInvalidValue;
     {
         ProfScope ps("tail_r.bf16", s);
-#define CTA_TAIL_R_GO(N)                                                                {                                                                                   auto kern = k_tail_r<N>;                                                        e = ensure_lds(kern, lds);                                                      if (e == hipSuccess) {                                                              kern<<<grid, CTA_WG, lds, s>>>(a);                                              e = hipGetLastError();                                                      }                                                                           }
-        if (j2t <= 2) CTA_TAIL_R_GO(2)
-        else if (j2t <= 4) CTA_TAIL_R_GO(4)
-        else if (j2t <= 8) CTA_TAIL_R_GO(8)
-        else if (j2t <= 16) CTA_TAIL_R_GO(16)
+        if (variant == 2) e = go_tail_pipe<true>(a, s, &grid);   // pipelined form where it fits
+        if (variant != 2 || e == hipErrorNotSupported) {
+            e = hipErrorInvalidValue;
+#define CTA_TAIL_R_GO(N)                                                        \
+            {                                                                   \
+                auto kern = k_tail_r<N>;                                        \
+                e = ensure_lds(kern, lds);                                      \
+                if (e == hipSuccess) {                                          \
+                    kern<<<grid, CTA_WG, lds, s>>>(a);                          \
+                    e = hipGetLastError();                                      \
+                }                                                               \
+            }
+            if (j2t <= 2) CTA_TAIL_R_GO(2)
+            else if (j2t <= 4) CTA_TAIL_R_GO(4)
+            else if (j2t <= 8) CTA_TAIL_R_GO(8)
+            else if (j2t <= 16) CTA_TAIL_R_GO(16)
 #undef CTA_TAIL_R_GO
+        }
     }
     if (e != hipSuccess) return e;
     return launch_finalize(partials, grid, scal, POST_RHO, nullptr, s);

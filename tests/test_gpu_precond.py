@@ -117,3 +117,20 @@ def test_tune_preconditioner_picks_a_converging_strength():
                        max_refine=80, precond=1)
     assert info["status"] == 0
     assert oracle.relative_residual(host(X), B, ref) <= 1.05e-8
+
+
+@pytest.mark.parametrize("tuning", [(0, 0, 0), (2, 2, 5)])
+def test_preconditioned_solve_with_pipelined_passes(tuning):
+    """Tail variant 2 (also the preconditioner's first pass with the residual
+    update), middle variant 2 and last variant 5 in the preconditioned
+    mixed-precision solve, judged by the oracle."""
+    torch = torch_cuda()
+    n = (16, 12, 40, 24)
+    p, ref, B = _setup(n, 1e-3, seed=4)
+    op = cta.Operator(p.A, p.D, p.lam)
+    op.set_preconditioner(1.6e-2)
+    cta.cta_op_set_tuning(op.handle, "bf16", *tuning)
+    X, info = op.solve(dev(B, torch.float64), precision="bf16_reliable", rtol=1e-8, inner_rtol=0.03,
+                       max_iter=3000, max_refine=80, precond=1)
+    assert info["status"] == 0, info
+    assert oracle.relative_residual(host(X), B, ref) <= 1.05e-8
