@@ -23,6 +23,8 @@ no blocking, fusion or reordering beyond what the cited definition states:
   convolutions, Table 1) with forward, backward (App. A.8) and Adam.
 * ``precond`` -- the tensor-inverse preconditioner (the separable part of the
   operator inverted mode by mode, Sec. 3) and preconditioned CG.
+* ``scattered`` -- the scattered-measurement operator of the application
+  (Sec. 6): Khatri-Rao rows (Sec. 2.2), normal operator as a CP sum.
 """
 from .tensor import mode_product, multi_mode_product, inner
 from .normal import (
@@ -40,11 +42,12 @@ from .dense import assemble, dense_solve
 from .judge import relative_residual
 from . import wsnet
 from . import precond
+from . import scattered
 
 __all__ = [
     "mode_product", "multi_mode_product", "inner",
     "gram", "reg_factor", "forward", "rhs", "normal_apply",
     "normal_apply_literal", "regulariser_apply", "NormalOperator",
     "cg", "CGResult", "lanczos_extremes",
-    "assemble", "dense_solve", "relative_residual", "wsnet",
+    "assemble", "dense_solve", "relative_residual", "wsnet", "precond", "scattered",
 ]

@@ -1,7 +1,7 @@
 """GPU parity of the band-aware normal operator (banded Gram factors).
 
 Cubic B-spline collocation factors give Gram matrices of half-bandwidth 3
-(each sample touches 4 basis functions per mode, Sec. 4), and the handle then
+(each sample touches 4 basis functions per mode, Sec. 6), and the handle then
 applies N in FP64/FP32 as banded streaming passes.  The banded result must
 match the FP64 oracle with the dense chain's bounds (FP64 1e-12, FP32 1e-5
 relative Frobenius) and the dense GPU chain to rounding.  Dense factors must

@@ -24,6 +24,14 @@ from .problems import (
     integer_tensor,
     CONFIGS,
 )
+from .scattered import (
+    SCATTERED,
+    ScatteredProblem,
+    scattered_sites,
+    scattered_problem,
+    scattered_config,
+    with_endpoints,
+)
 
 __all__ = [
     "collocation_matrix",
@@ -39,4 +47,10 @@ __all__ = [
     "warmstart_problem",
     "integer_tensor",
     "CONFIGS",
+    "SCATTERED",
+    "ScatteredProblem",
+    "scattered_sites",
+    "scattered_problem",
+    "scattered_config",
+    "with_endpoints",
 ]
