@@ -354,6 +354,58 @@ cta_status cta_ws_adam_step(cta_ws w, float lr, float beta1, float beta2, float 
 cta_status cta_ws_params(cta_ws w, void* host_buf, size_t bytes, int set, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Scattered-measurement operator (Sec. 6, the paper's application): the
+ * coefficients X (order N in [2, 4], extents n_k >= 4, row-major) of a cubic
+ * B-spline field (clamped uniform knots on [0, 1], n_k functions per mode)
+ * are observed at `count` scattered sites t^i in [0, 1]^N.  Row i of the
+ * system is the Khatri-Rao product a_i = b^i_1 (x) ... (x) b^i_N of the basis
+ * rows of its coordinates (the repeated-index product of Sec. 2.2), so
+ *   forward:  y_i = <a_i, X>,            adjoint:  B = sum_i y_i a_i,
+ *   normal:   N(X) = sum_i a_i <a_i, X> + lam * sum_k X x_k (D_k^T D_k),
+ * the CANDECOMP sum of Sec. 6 plus the Kronecker-sum regulariser.  Neither N
+ * nor its CP factors are stored: the kernels evaluate the basis from the
+ * sites.  Sites are sorted into bricks of knot-span cells at creation; each
+ * brick's coefficient tile is worked on in LDS and written to a scratch slot
+ * of its own, and a second pass sums the slots covering each coefficient in a
+ * fixed order (no global atomics; the order of the LDS additions within a
+ * tile is not fixed, so results may differ between calls by rounding).
+ *
+ * cta_sop_create: host_coords (host, float32, mode-major: coordinate k of
+ * site i at [k * count + i]) must lie in [0, 1] (CTA_ERR_ARG otherwise);
+ * host_D[k] (host, row-major d_rows[k] x n[k], FP64) is the regulariser
+ * factor of mode k, or NULL / host_D NULL for none; D_k^T D_k must have
+ * half-bandwidth <= 2 (second differences; CTA_ERR_UNSUPPORTED otherwise).
+ * count may be 0 (then N is the regulariser alone).  Synchronous; the
+ * handle owns its device memory (sites, permutation, bricks, bands and, on
+ * first use per dtype, the tile scratch and CG vectors).
+ * Device arrays: X, B, P, Q of n_1 * .. * n_N elements, y of `count`
+ * elements in the caller's site order, all of dtype CTA_F64 or CTA_F32 (the
+ * arithmetic precision).  dot (device, FP64, or NULL) receives <P, Q>.
+ * Calls are enqueued on `stream`; one handle must not be used from two
+ * streams at once (the scratch tiles are shared).
+ * ---------------------------------------------------------------------- */
+typedef struct cta_sop_s* cta_sop;
+
+cta_status cta_sop_create(cta_sop* out, int order, const int64_t* n, int64_t count,
+                          const float* host_coords, const double* const* host_D,
+                          const int64_t* d_rows, double lam);
+cta_status cta_sop_destroy(cta_sop op);
+/* host_out8: brick cells per mode (4 entries, 0 past the order), tile
+ * elements, chunks (workgroups of the brick pass), bricks, device bytes. */
+cta_status cta_sop_layout(cta_sop op, int64_t* host_out8);
+cta_status cta_sop_forward(cta_sop op, const void* X, void* y, cta_dtype dtype, void* stream);
+cta_status cta_sop_adjoint(cta_sop op, const void* y, void* B, cta_dtype dtype, void* stream);
+cta_status cta_sop_apply_normal(cta_sop op, const void* P, void* Q, cta_dtype dtype, double* dot,
+                                void* stream);
+/* Tensor CG (Fig. Tensor_CG) on the scattered normal operator from X = 0 in
+ * the dtype's precision, stopping when ||r|| <= rtol ||B|| (recursive
+ * residual), at most max_iter iterations; the host reads the flag every
+ * check_every iterations.  Fills *host_info (rel_res_true recomputed in the
+ * dtype's precision).  Returns CTA_OK, CTA_NOT_CONVERGED or an error. */
+cta_status cta_sop_cg_solve(cta_sop op, const void* B, void* X, cta_dtype dtype, double rtol,
+                            int max_iter, int check_every, cta_cg_info* host_info, void* stream);
+
+/* ------------------------------------------------------------------------
  * Kernel timing tracer.  When enabled, every kernel the library launches is
  * bracketed by two HIP events recorded on the launch's stream (so the timing
  * is of the kernel as it ran inside the caller's work).  cta_prof_read

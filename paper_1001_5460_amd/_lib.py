@@ -101,6 +101,15 @@ _SIGS = {
     "cta_op_set_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "cta_op_set_banded": (ctypes.c_int, [_P, ctypes.c_int]),
     "cta_op_band_width": (ctypes.c_int, [_P]),
+    "cta_sop_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _I64P, ctypes.c_int64, _P,
+                                      ctypes.POINTER(_P), _I64P, ctypes.c_double]),
+    "cta_sop_destroy": (ctypes.c_int, [_P]),
+    "cta_sop_layout": (ctypes.c_int, [_P, _I64P]),
+    "cta_sop_forward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
+    "cta_sop_adjoint": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
+    "cta_sop_apply_normal": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P]),
+    "cta_sop_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_int, ctypes.POINTER(_CgInfo), _P]),
     "cta_prof_enable": (ctypes.c_int, [ctypes.c_int]),
     "cta_prof_reset": (ctypes.c_int, []),
     "cta_prof_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t,
@@ -551,4 +560,125 @@ class Operator:
         if X is None:
             X = torch.zeros_like(B)
         info = cta_cg_solve(self.handle, B, X, stream, **opts)
+        return X, info
+
+
+# ---------------------------------------------------------------- scattered operator
+def cta_sop_create(coords, n, D, lam):
+    """Handle of the scattered-measurement operator: ``coords`` (order, count)
+    host float32 sites in [0, 1], extents ``n``, host factors D_k (or None)."""
+    lib = load_library()
+    c = np.ascontiguousarray(coords, dtype=np.float32)
+    order = len(n)
+    if c.ndim != 2 or c.shape[0] != order:
+        raise CtaError(-1, "coords must have shape (order, count)")
+    keep = [c]
+    if D is not None:
+        D64 = [np.ascontiguousarray(d, dtype=np.float64) if d is not None
+               else np.zeros((0, int(n[k]))) for k, d in enumerate(D)]
+        keep.append(D64)
+        d_ptrs = (ctypes.c_void_p * order)(*[d.ctypes.data if d.size else None for d in D64])
+        p = _i64([d.shape[0] for d in D64])
+    else:
+        d_ptrs = None
+        p = None
+    h = ctypes.c_void_p()
+    _check(lib.cta_sop_create(ctypes.byref(h), order, _i64(n), int(c.shape[1]),
+                              c.ctypes.data if c.size else None, d_ptrs, p, float(lam)))
+    return h
+
+
+def cta_sop_destroy(h):
+    if h:
+        load_library().cta_sop_destroy(h)
+
+
+def cta_sop_layout(h):
+    out = (ctypes.c_int64 * 8)()
+    _check(load_library().cta_sop_layout(h, out))
+    v = list(out)
+    return {"brick_cells": v[:4], "tile": v[4], "chunks": v[5], "bricks": v[6], "device_bytes": v[7]}
+
+
+def cta_sop_forward(h, X, y, stream=None):
+    _check(load_library().cta_sop_forward(h, _dev(X, "X"), _dev(y, "y") if y.numel() else None,
+                                          _dt(X), _stream(stream)))
+    return y
+
+
+def cta_sop_adjoint(h, y, B, stream=None):
+    _check(load_library().cta_sop_adjoint(h, _dev(y, "y") if y.numel() else None, _dev(B, "B"),
+                                          _dt(B), _stream(stream)))
+    return B
+
+
+def cta_sop_apply_normal(h, P, Q, dot=None, stream=None):
+    dptr = _dev(dot, "dot") if dot is not None else None
+    _check(load_library().cta_sop_apply_normal(h, _dev(P, "P"), _dev(Q, "Q"), _dt(P), dptr,
+                                               _stream(stream)))
+    return Q
+
+
+def cta_sop_cg_solve(h, B, X, rtol=1e-6, max_iter=10000, check_every=16, stream=None):
+    info = _CgInfo()
+    st = load_library().cta_sop_cg_solve(h, _dev(B, "B"), _dev(X, "X"), _dt(B), float(rtol),
+                                         int(max_iter), int(check_every), ctypes.byref(info),
+                                         _stream(stream))
+    _check(st, allow_not_converged=True)
+    return _info_dict(info)
+
+
+class ScatteredOperator:
+    """Owning wrapper of a cta_sop handle (sites, extents, D_k, lam)."""
+
+    def __init__(self, coords, n, D, lam):
+        self.n = tuple(int(v) for v in n)
+        self.count = int(np.asarray(coords).shape[1])
+        self.lam = float(lam)
+        self.handle = cta_sop_create(coords, self.n, D, lam)
+
+    def close(self):
+        if self.handle:
+            cta_sop_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def layout(self):
+        return cta_sop_layout(self.handle)
+
+    def forward(self, X, y=None, stream=None):
+        torch = _torch()
+        if tuple(X.shape) != self.n:
+            raise CtaError(-2, f"X has shape {tuple(X.shape)}, expected {self.n}")
+        if y is None:
+            y = torch.empty(self.count, dtype=X.dtype, device=X.device)
+        return cta_sop_forward(self.handle, X, y, stream)
+
+    def rhs(self, y, B=None, stream=None):
+        torch = _torch()
+        if y.numel() != self.count:
+            raise CtaError(-2, f"y has {y.numel()} entries, expected {self.count}")
+        if B is None:
+            B = torch.empty(self.n, dtype=y.dtype, device=y.device)
+        return cta_sop_adjoint(self.handle, y, B, stream)
+
+    def apply(self, P, Q=None, dot=None, stream=None):
+        torch = _torch()
+        if tuple(P.shape) != self.n:
+            raise CtaError(-2, f"P has shape {tuple(P.shape)}, expected {self.n}")
+        if Q is None:
+            Q = torch.empty_like(P)
+        return cta_sop_apply_normal(self.handle, P, Q, dot, stream)
+
+    def solve(self, B, X=None, rtol=1e-6, max_iter=10000, check_every=16, stream=None):
+        torch = _torch()
+        if X is None:
+            X = torch.empty_like(B)
+        info = cta_sop_cg_solve(self.handle, B, X, rtol, max_iter, check_every, stream)
         return X, info

@@ -166,4 +166,34 @@ hipError_t launch_fill_pattern(int tv, void* x, int64_t n, hipStream_t s);
 // X64 += (double) d32
 hipError_t launch_add_f64(double* X, const void* d, int td, int64_t n, hipStream_t s);
 
+// ---------------------------------------------------------------- scattered operator
+// Brick geometry of the scattered-measurement operator (order N <= 4).  A
+// cell is one knot span per mode (C_k = n_k - 3 spans); a brick holds bc_k
+// cells per mode and touches a tile of te_k = bc_k + 3 coefficients per mode
+// (row-major, strides ts, tile = prod te).  gs: row-major strides of the
+// coefficient tensor; roff: first row of mode k in the regulariser band table.
+struct SopGeom {
+    int N;
+    int n[4], C[4], bc[4], nb[4], te[4], ts[4], roff[4];
+    int64_t gs[4];
+    int tile;
+    int64_t ncoef;
+};
+enum { SOP_FWD = 0, SOP_ADJ = 1, SOP_NRM = 2 };
+
+// One workgroup per chunk: y = A X (FWD, y in the caller's site order), or the
+// chunk's tile of A^T y (ADJ) or A^T A X (NRM) into tiles[chunk].
+hipError_t launch_sop_brick(int dt, int mode, const SopGeom& g, const float* coords, int64_t S,
+                            const int* perm, const int* cstart, const int* cbrick, int nchunks,
+                            const void* X, const void* yin, void* yout, void* tiles,
+                            const CgScalars* scal, hipStream_t s);
+// Q = sum of covering tiles (+ lam * regulariser(P) and <P, Q> partials when P
+// is given; the finalize kernel then applies `post`).
+hipError_t launch_sop_gather(int dt, const SopGeom& g, const void* tiles, const int* bchunk0, const void* P,
+                             const void* rb, double lam, void* Q, double* partials, CgScalars* scal, int post,
+                             double* out, hipStream_t s);
+// x += alpha p; p = r + beta p (scalars on the device; skipped once done)
+hipError_t launch_sop_pstep(int dt, void* x, void* p, const void* r, int64_t n, const CgScalars* scal,
+                            hipStream_t s);
+
 }  // namespace cta

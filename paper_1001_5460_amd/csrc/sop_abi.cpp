@@ -1,0 +1,387 @@
+// C ABI of the scattered-measurement operator (Sec. 6): handle set-up (sites
+// sorted into bricks of knot-span cells), forward model, adjoint, normal
+// operator and the tensor CG of Fig. Tensor_CG on it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "abi_internal.hpp"
+
+using namespace cta;
+
+namespace {
+
+// Sites per chunk: one workgroup stages a brick's tile once per chunk.
+constexpr int kSopChunk = 4096;
+// Elements of one coefficient tile: the normal operator keeps two tiles in
+// LDS (64 KB in FP32, 128 KB in FP64).
+constexpr int kSopTileMax = 8192;
+
+}  // namespace
+
+struct cta_sop_s {
+    int order = 0;
+    int64_t n[4] = {0, 0, 0, 0};
+    int64_t S = 0;
+    double lam = 0.0;
+    SopGeom g{};
+    int nchunks = 0;
+    int nbricks = 0;
+    float* coords = nullptr;  // (order, S) sorted by brick
+    int* perm = nullptr;      // sorted position -> caller's site index
+    int* cstart = nullptr;    // nchunks + 1 site offsets
+    int* cbrick = nullptr;    // brick of each chunk
+    int* bchunk0 = nullptr;   // nbricks + 1 chunk offsets
+    void* rb[2] = {nullptr, nullptr};  // regulariser bands (F64, F32): 5 per row
+    void* tiles[2] = {nullptr, nullptr};
+    void* vec[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};  // r, p, q
+    CgScalars* scal = nullptr;
+    CgScalars* hscal = nullptr;
+    double* partials = nullptr;
+    std::vector<void*> allocs;
+    size_t dev_bytes = 0;
+};
+
+namespace {
+
+cta_status salloc(cta_sop_s* op, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return fail(CTA_ERR_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    op->allocs.push_back(*p);
+    op->dev_bytes += bytes;
+    return CTA_OK;
+}
+
+cta_status upload(cta_sop_s* op, void** dst, const void* src, size_t bytes) {
+    cta_status st = salloc(op, dst, bytes);
+    if (st != CTA_OK) return st;
+    if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(CTA_ERR_HIP, "copy to the device failed");
+    return CTA_OK;
+}
+
+void destroy(cta_sop_s* op) {
+    for (void* p : op->allocs) (void)hipFree(p);
+    if (op->hscal) (void)hipHostFree(op->hscal);
+    delete op;
+}
+
+// Brick shape: start from one cell per mode and double the modes in turn
+// (last mode first) while the tile of (bc_k + 3) coefficients per mode stays
+// within kSopTileMax elements.
+void choose_bricks(SopGeom& g) {
+    for (int k = 0; k < g.N; ++k) g.bc[k] = 1;
+    auto tile = [&g](const int* bc) {
+        int64_t t = 1;
+        for (int k = 0; k < g.N; ++k) t *= bc[k] + 3;
+        return t;
+    };
+    bool grew = true;
+    while (grew) {
+        grew = false;
+        for (int k = g.N - 1; k >= 0; --k) {
+            if (g.bc[k] >= g.C[k]) continue;
+            int trial[4] = {g.bc[0], g.bc[1], g.bc[2], g.bc[3]};
+            trial[k] = std::min(2 * g.bc[k], g.C[k]);
+            if (tile(trial) <= kSopTileMax) {
+                g.bc[k] = trial[k];
+                grew = true;
+            }
+        }
+    }
+    int64_t t = 1;
+    for (int k = g.N - 1; k >= 0; --k) {
+        g.nb[k] = (g.C[k] + g.bc[k] - 1) / g.bc[k];
+        g.te[k] = g.bc[k] + 3;
+        g.ts[k] = (int)t;
+        t *= g.te[k];
+    }
+    g.tile = (int)t;
+}
+
+int dtype_index(cta_dtype d) { return d == CTA_F64 ? 0 : (d == CTA_F32 ? 1 : -1); }
+
+cta_status ensure_tiles(cta_sop_s* op, int di) {
+    if (op->tiles[di] || op->nchunks == 0) return CTA_OK;
+    const size_t bytes = (size_t)op->nchunks * op->g.tile * (di == 0 ? 8 : 4);
+    return salloc(op, &op->tiles[di], bytes);
+}
+
+cta_status ensure_vectors(cta_sop_s* op, int di) {
+    for (int v = 0; v < 3; ++v)
+        if (!op->vec[di][v]) {
+            cta_status st = salloc(op, &op->vec[di][v], (size_t)op->g.ncoef * (di == 0 ? 8 : 4));
+            if (st != CTA_OK) return st;
+        }
+    return CTA_OK;
+}
+
+#define SOP_HIP(x)                                                                               \
+    do {                                                                                         \
+        hipError_t e_ = (x);                                                                     \
+        if (e_ != hipSuccess) return fail(CTA_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_));    \
+    } while (0)
+#define SOP_TRY(x)                     \
+    do {                               \
+        cta_status st_ = (x);          \
+        if (st_ != CTA_OK) return st_; \
+    } while (0)
+
+// Q = A^T A P + lam * sum_k P x_k R_k; <P, Q> handled by `post` (gated by the
+// solve's done flag when `gated`).
+cta_status sop_normal(cta_sop_s* op, int di, const void* P, void* Q, int post, double* out, bool gated,
+                      hipStream_t s) {
+    const int dt = di == 0 ? DT_F64 : DT_F32;
+    SOP_TRY(ensure_tiles(op, di));
+    const CgScalars* gate = gated ? op->scal : nullptr;
+    SOP_HIP(launch_sop_brick(dt, SOP_NRM, op->g, op->coords, op->S, op->perm, op->cstart, op->cbrick,
+                             op->nchunks, P, nullptr, nullptr, op->tiles[di], gate, s));
+    SOP_HIP(launch_sop_gather(dt, op->g, op->tiles[di], op->bchunk0, P, op->rb[di], op->lam, Q,
+                              post == POST_NONE ? nullptr : op->partials, gated ? op->scal : nullptr, post,
+                              out, s));
+    return CTA_OK;
+}
+
+cta_status read_scal(cta_sop_s* op, hipStream_t s) {
+    if (hipMemcpyAsync(op->hscal, op->scal, sizeof(CgScalars), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(CTA_ERR_HIP, "scalar readback failed");
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(CTA_ERR_HIP, "stream synchronize failed");
+    return CTA_OK;
+}
+
+}  // namespace
+
+extern "C" cta_status cta_sop_create(cta_sop* out, int order, const int64_t* n, int64_t count,
+                                     const float* host_coords, const double* const* host_D,
+                                     const int64_t* d_rows, double lam) {
+    if (!out || !n) return fail(CTA_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (order < 2 || order > 4) return fail(CTA_ERR_UNSUPPORTED, "scattered operator: order must be 2, 3 or 4");
+    if (count < 0 || count >= ((int64_t)1 << 31)) return fail(CTA_ERR_ARG, "site count out of range");
+    if (count > 0 && !host_coords) return fail(CTA_ERR_ARG, "NULL coordinates");
+    if (!std::isfinite(lam)) return fail(CTA_ERR_ARG, "lambda must be finite");
+    int64_t ncoef = 1;
+    for (int k = 0; k < order; ++k) {
+        if (n[k] < 4 || n[k] > (1 << 20)) return fail(CTA_ERR_SHAPE, "n[%d] must be in [4, 2^20] (cubic basis)", k);
+        ncoef *= n[k];
+        if (ncoef > ((int64_t)1 << 34)) return fail(CTA_ERR_SHAPE, "too many coefficients");
+    }
+    for (int64_t i = 0; i < count * order; ++i) {
+        const float t = host_coords[i];
+        if (!(t >= 0.0f && t <= 1.0f)) return fail(CTA_ERR_ARG, "site coordinate %lld outside [0, 1]", (long long)i);
+    }
+    cta_sop_s* op = new cta_sop_s();
+    op->order = order;
+    op->S = count;
+    op->lam = lam;
+    SopGeom& g = op->g;
+    g.N = order;
+    g.ncoef = ncoef;
+    int64_t stride = 1, roff = 0;
+    for (int k = order - 1; k >= 0; --k) {
+        op->n[k] = n[k];
+        g.n[k] = (int)n[k];
+        g.C[k] = (int)n[k] - 3;
+        g.gs[k] = stride;
+        stride *= n[k];
+    }
+    for (int k = 0; k < order; ++k) {
+        g.roff[k] = (int)roff;
+        roff += n[k];
+    }
+    choose_bricks(g);
+    int64_t nbr = 1;
+    for (int k = 0; k < order; ++k) nbr *= g.nb[k];
+    if (nbr >= ((int64_t)1 << 26)) {
+        destroy(op);
+        return fail(CTA_ERR_SHAPE, "too many bricks");
+    }
+    op->nbricks = (int)nbr;
+
+    // regulariser bands of R_k = D_k^T D_k (half-bandwidth <= 2)
+    std::vector<double> band64((size_t)roff * 5, 0.0);
+    for (int k = 0; k < order; ++k) {
+        if (!host_D || !host_D[k] || !d_rows || d_rows[k] <= 0) continue;
+        const int64_t nk = n[k], rows = d_rows[k];
+        const double* D = host_D[k];
+        for (int64_t i = 0; i < nk; ++i)
+            for (int64_t j = 0; j < nk; ++j) {
+                double v = 0.0;
+                for (int64_t r = 0; r < rows; ++r) v += D[r * nk + i] * D[r * nk + j];
+                if (v == 0.0) continue;
+                if (std::llabs(i - j) > 2) {
+                    destroy(op);
+                    return fail(CTA_ERR_UNSUPPORTED, "D_%d^T D_%d has half-bandwidth > 2", k, k);
+                }
+                band64[(size_t)(g.roff[k] + i) * 5 + (size_t)(j - i + 2)] = v;
+            }
+    }
+    std::vector<float> band32(band64.begin(), band64.end());
+
+    // sort the sites by brick (counting sort, stable) and cut bricks into chunks
+    std::vector<int> brick_of((size_t)count);
+    std::vector<int64_t> bcount((size_t)nbr + 1, 0);
+    for (int64_t i = 0; i < count; ++i) {
+        int64_t b = 0;
+        for (int k = 0; k < order; ++k) {
+            const double x = (double)host_coords[(size_t)k * count + i] * g.C[k];
+            int s = (int)x;
+            s = std::min(std::max(s, 0), g.C[k] - 1);
+            b = b * g.nb[k] + s / g.bc[k];
+        }
+        brick_of[i] = (int)b;
+        bcount[b + 1] += 1;
+    }
+    for (int64_t b = 0; b < nbr; ++b) bcount[b + 1] += bcount[b];
+    std::vector<int> perm((size_t)count);
+    {
+        std::vector<int64_t> pos(bcount.begin(), bcount.end() - 1);
+        for (int64_t i = 0; i < count; ++i) perm[pos[brick_of[i]]++] = (int)i;
+    }
+    std::vector<float> sorted((size_t)count * order);
+    for (int k = 0; k < order; ++k)
+        for (int64_t i = 0; i < count; ++i) sorted[(size_t)k * count + i] = host_coords[(size_t)k * count + perm[i]];
+    std::vector<int> cstart, cbrick, bchunk0((size_t)nbr + 1, 0);
+    for (int64_t b = 0; b < nbr; ++b) {
+        bchunk0[b] = (int)cbrick.size();
+        for (int64_t lo = bcount[b]; lo < bcount[b + 1]; lo += kSopChunk) {
+            cstart.push_back((int)lo);
+            cbrick.push_back((int)b);
+        }
+    }
+    bchunk0[nbr] = (int)cbrick.size();
+    cstart.push_back((int)count);
+    op->nchunks = (int)cbrick.size();
+
+    cta_status st = CTA_OK;
+    if (st == CTA_OK) st = upload(op, (void**)&op->coords, sorted.data(), sorted.size() * sizeof(float));
+    if (st == CTA_OK) st = upload(op, (void**)&op->perm, perm.data(), perm.size() * sizeof(int));
+    if (st == CTA_OK) st = upload(op, (void**)&op->cstart, cstart.data(), cstart.size() * sizeof(int));
+    if (st == CTA_OK) st = upload(op, (void**)&op->cbrick, cbrick.data(), cbrick.size() * sizeof(int));
+    if (st == CTA_OK) st = upload(op, (void**)&op->bchunk0, bchunk0.data(), bchunk0.size() * sizeof(int));
+    if (st == CTA_OK) st = upload(op, &op->rb[0], band64.data(), band64.size() * sizeof(double));
+    if (st == CTA_OK) st = upload(op, &op->rb[1], band32.data(), band32.size() * sizeof(float));
+    if (st == CTA_OK) st = salloc(op, (void**)&op->scal, sizeof(CgScalars));
+    if (st == CTA_OK) st = salloc(op, (void**)&op->partials, kMaxGrid * sizeof(double));
+    if (st == CTA_OK && hipHostMalloc((void**)&op->hscal, sizeof(CgScalars), hipHostMallocDefault) != hipSuccess)
+        st = fail(CTA_ERR_NOMEM, "pinned host allocation failed");
+    if (st == CTA_OK && hipMemset(op->scal, 0, sizeof(CgScalars)) != hipSuccess)
+        st = fail(CTA_ERR_HIP, "clearing the scalars failed");
+    if (st != CTA_OK) {
+        destroy(op);
+        return st;
+    }
+    *out = op;
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_sop_destroy(cta_sop op) {
+    if (op) destroy(op);
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_sop_layout(cta_sop op, int64_t* host_out8) {
+    if (!op || !host_out8) return fail(CTA_ERR_ARG, "NULL argument");
+    for (int k = 0; k < 4; ++k) host_out8[k] = k < op->order ? op->g.bc[k] : 0;
+    host_out8[4] = op->g.tile;
+    host_out8[5] = op->nchunks;
+    host_out8[6] = op->nbricks;
+    host_out8[7] = (int64_t)op->dev_bytes;
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_sop_forward(cta_sop op, const void* X, void* y, cta_dtype dtype, void* stream) {
+    if (!op || !X || (!y && op->S > 0)) return fail(CTA_ERR_ARG, "NULL argument");
+    const int di = dtype_index(dtype);
+    if (di < 0) return fail(CTA_ERR_DTYPE, "scattered operator: dtype must be CTA_F64 or CTA_F32");
+    SOP_HIP(launch_sop_brick(di == 0 ? DT_F64 : DT_F32, SOP_FWD, op->g, op->coords, op->S, op->perm, op->cstart,
+                             op->cbrick, op->nchunks, X, nullptr, y, nullptr, nullptr, (hipStream_t)stream));
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_sop_adjoint(cta_sop op, const void* y, void* B, cta_dtype dtype, void* stream) {
+    if (!op || !B || (!y && op->S > 0)) return fail(CTA_ERR_ARG, "NULL argument");
+    const int di = dtype_index(dtype);
+    if (di < 0) return fail(CTA_ERR_DTYPE, "scattered operator: dtype must be CTA_F64 or CTA_F32");
+    const int dt = di == 0 ? DT_F64 : DT_F32;
+    hipStream_t s = (hipStream_t)stream;
+    SOP_TRY(ensure_tiles(op, di));
+    SOP_HIP(launch_sop_brick(dt, SOP_ADJ, op->g, op->coords, op->S, op->perm, op->cstart, op->cbrick, op->nchunks,
+                             nullptr, y, nullptr, op->tiles[di], nullptr, s));
+    SOP_HIP(launch_sop_gather(dt, op->g, op->tiles[di], op->bchunk0, nullptr, nullptr, 0.0, B, nullptr, nullptr,
+                              POST_NONE, nullptr, s));
+    return CTA_OK;
+}
+
+extern "C" cta_status cta_sop_apply_normal(cta_sop op, const void* P, void* Q, cta_dtype dtype, double* dot,
+                                           void* stream) {
+    if (!op || !P || !Q) return fail(CTA_ERR_ARG, "NULL argument");
+    if (P == Q) return fail(CTA_ERR_ARG, "P and Q must not overlap");
+    const int di = dtype_index(dtype);
+    if (di < 0) return fail(CTA_ERR_DTYPE, "scattered operator: dtype must be CTA_F64 or CTA_F32");
+    return sop_normal(op, di, P, Q, dot ? POST_DOT : POST_NONE, dot, false, (hipStream_t)stream);
+}
+
+extern "C" cta_status cta_sop_cg_solve(cta_sop op, const void* B, void* X, cta_dtype dtype, double rtol,
+                                       int max_iter, int check_every, cta_cg_info* info, void* stream) {
+    if (!op || !B || !X || !info) return fail(CTA_ERR_ARG, "NULL argument");
+    if (B == X) return fail(CTA_ERR_ARG, "B and X must not overlap");
+    if (!(rtol >= 0) || max_iter < 0) return fail(CTA_ERR_ARG, "bad rtol or max_iter");
+    const int di = dtype_index(dtype);
+    if (di < 0) return fail(CTA_ERR_DTYPE, "scattered operator: dtype must be CTA_F64 or CTA_F32");
+    std::memset(info, 0, sizeof *info);
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    const int dt = di == 0 ? DT_F64 : DT_F32;
+    const int64_t n = op->g.ncoef;
+    const size_t vb = (size_t)n * (di == 0 ? 8 : 4);
+    SOP_TRY(ensure_vectors(op, di));
+    void *r = op->vec[di][0], *p = op->vec[di][1], *q = op->vec[di][2];
+    if (check_every < 1) check_every = 16;
+    // X = 0, r = B, rho = <B, B>
+    SOP_HIP(launch_dot(dt, B, B, n, op->partials, op->scal, &op->scal->bnorm2, s));
+    SOP_HIP(launch_fill_zero(X, vb, s));
+    SOP_HIP(launch_cast(dt, dt, B, r, n, s));
+    SOP_HIP(launch_dot(dt, r, r, n, op->partials, op->scal, &op->scal->rho, s));
+    SOP_HIP(launch_fill_zero(p, vb, s));
+    SOP_HIP(launch_cg_setup(op->scal, rtol * rtol, max_iter, s, 0));
+    // each step: x += alpha p (previous step) and p = r + beta p; q = N p and
+    // alpha = rho / <p, q>; r -= alpha q, rho and the stopping test
+    for (;;) {
+        for (int c = 0; c < check_every; ++c) {
+            SOP_HIP(launch_sop_pstep(dt, X, p, r, n, op->scal, s));
+            SOP_TRY(sop_normal(op, di, p, q, POST_ALPHA, nullptr, true, s));
+            SOP_HIP(launch_cg_update(dt, nullptr, r, p, q, n, op->partials, op->scal, s));
+        }
+        SOP_TRY(read_scal(op, s));
+        if (op->hscal->done != DONE_RUNNING) break;
+    }
+    SOP_HIP(launch_x_flush(dt, X, p, n, op->scal, s));
+    const int done = op->hscal->done;
+    const double bn2 = op->hscal->bnorm2;
+    info->iters = op->hscal->iters;
+    info->rel_res_recursive = std::sqrt(std::max(0.0, op->hscal->rho) / std::max(bn2, 1e-300));
+    // true residual ||B - N X|| in the solve's precision
+    SOP_TRY(sop_normal(op, di, X, q, POST_NONE, nullptr, false, s));
+    SOP_HIP(launch_residual(dt, dt, B, q, r, n, op->partials, op->scal, &op->scal->dot, s));
+    SOP_TRY(read_scal(op, s));
+    info->rel_res_true = bn2 > 0 ? std::sqrt(op->hscal->dot / bn2) : std::sqrt(op->hscal->dot);
+    info->refine_steps = 0;
+    cta_status st = CTA_OK;
+    if (done == DONE_BREAKDOWN)
+        st = CTA_ERR_BREAKDOWN;
+    else if (done != DONE_CONVERGED)
+        st = CTA_NOT_CONVERGED;
+    info->status = st;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
