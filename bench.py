@@ -123,15 +123,20 @@ def ensure_library():
     return cta
 
 
+def _host_threads():
+    """Threads the host's BLAS pool runs the oracle with."""
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()]))
+    except Exception:
+        return int(os.cpu_count())
+
+
 def cpu_baseline(p, X_gpu_host, iters=3, X_extra=None):
     """The FP64 oracle on the host cores: a few CG iterations of the full problem,
     plus the oracle's residual judge of the GPU solution (both outside the timed region)."""
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
+    cores = _host_threads()
     op = oracle.NormalOperator(p.A, p.D, p.lam)
     Y = op.forward(p.X_true) + p.noise
     B = op.rhs(Y)
@@ -304,6 +309,111 @@ def run_warmstart(args, cta, torch, seeds, reps=5):
     return out
 
 
+def run_scattered(args, cta, torch):
+    """The paper's application size (Sec. 6): 128x128x128x16 cubic-spline
+    coefficients (33,554,432 unknowns) fitted to 9,000,000 uniform scattered
+    sites, second-difference regulariser with lambda 1e-3, FP32 CG from zero
+    to --sop-rtol.  One step is the right-hand side (adjoint of the data) plus
+    the solve; the operator set-up (site sort) is outside the timed region."""
+    import workload
+    dev = torch.device("cuda:0")
+    p = workload.scattered_config()
+    t = time.perf_counter()
+    op = cta.ScatteredOperator(p.coords, p.n, p.D, p.lam)
+    setup_s = time.perf_counter() - t
+    dt = torch.float32
+    Xt = torch.from_numpy(p.X_true).to(dev, dt)
+    y = op.forward(Xt)
+    y += torch.from_numpy(p.noise).to(dev, dt)
+    del Xt
+    rtol, max_iter = args.sop_rtol, args.sop_max_iter
+    B = op.rhs(y)
+    X, info = op.solve(B, rtol=rtol, max_iter=max_iter)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        op.rhs(y, B)
+        X, info = op.solve(B, X, rtol=rtol, max_iter=max_iter)
+    torch.cuda.synchronize()
+    solve_s = (time.perf_counter() - t0) / args.steps
+    # per-kernel durations of one traced solve
+    cta.cta_prof_reset()
+    cta.cta_prof_enable(True)
+    op.rhs(y, B)
+    op.solve(B, X, rtol=rtol, max_iter=max_iter)
+    torch.cuda.synchronize()
+    prof = cta.cta_prof_read()
+    cta.cta_prof_enable(False)
+    kern = {}
+    for name, r in prof.items():
+        cnt = r.get("active_count", r["count"])
+        ms = r.get("active_ms", r["total_ms"])
+        kern[name] = {"count": r["count"], "active": cnt, "avg_ms": round(ms / max(cnt, 1), 4)}
+    # standalone normal-operator applies in both precisions
+    apply_ms = {}
+    for name, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        P = torch.randn(p.n, dtype=tdt, device=dev)
+        Q = torch.empty_like(P)
+        op.apply(P, Q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            op.apply(P, Q)
+        torch.cuda.synchronize()
+        apply_ms[name] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+        del P, Q
+    # roofline of the brick pass (dominant): LDS traffic of the 4^N window
+    # gathers (4 B each) and FP64 LDS atomic adds (8 B each) per site over the
+    # kernel's average duration, against the LDS bandwidth 128 B/clk/CU x 256 CUs
+    # x 2.4 GHz = 78.6 TB/s
+    S, win = p.count, 4 ** len(p.n)
+    brick = kern.get("sop_brick.f32", {"avg_ms": float("nan")})
+    lds_bytes = S * win * (4 + 8)
+    achieved = lds_bytes / (brick["avg_ms"] * 1e-3) / 1e9
+    roof = {"bound": "lds", "kernel": "sop_brick.f32", "achieved": round(achieved, 1), "peak": 78643.2,
+            "unit": "GB/s", "frac": round(achieved / 78643.2, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": lds_bytes, "avg_launch_ms": brick["avg_ms"]}
+    out = {
+        "metric": f"time to {rtol:g} relative residual, scattered-data spline fit (FP32 CG)",
+        "value": round(solve_s, 4), "unit": "s per solve (rhs + CG)", "higher_is_better": False,
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "scattered_4d_128x128x128x16_9M_sites", "unknowns": int(np.prod(p.n)),
+                   "sites": S, "lam": p.lam, "rtol": rtol},
+        "iters_per_solve": info["iters"], "status": info["status"],
+        "rel_res_true": info["rel_res_true"], "cg_iters_per_s": round(info["iters"] / solve_s, 1),
+        "normal_apply_ms": apply_ms, "setup_s": round(setup_s, 3), "layout": op.layout,
+        "kernels": kern, "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = scattered_cpu_baseline(p, apply_ms["f64"])
+    print(json.dumps(out), flush=True)
+
+
+def scattered_cpu_baseline(p, gpu_f64_ms, sample=200_000):
+    """The FP64 oracle's normal-operator apply on the host: the data term on a
+    bounded sample of the sites (time scaled to all sites) plus the regulariser
+    over the whole tensor."""
+    import oracle
+    from oracle import scattered as osc
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal(p.n)
+    sub = p.coords[:, :sample]
+    t = time.perf_counter()
+    rows = osc.sample_rows(sub, p.n)
+    osc.adjoint(osc.forward(X, sub, rows), sub, p.n, rows)
+    t_sites = time.perf_counter() - t
+    R = [oracle.reg_factor(d) for d in p.D]
+    t = time.perf_counter()
+    oracle.regulariser_apply(X, R, p.lam)
+    t_reg = time.perf_counter() - t
+    est = t_sites * p.count / sample + t_reg
+    return {"value": round(1.0 / est, 5), "unit": "normal-operator applies/s", "cores": _host_threads(),
+            "kind": "oracle",
+            "sample": f"oracle.scattered forward + adjoint on {sample} of the {p.count} sites (scaled), "
+                      "plus the regulariser on the full 128x128x128x16 tensor, NumPy on the host",
+            "seconds": round(t_sites + t_reg, 3), "gpu_f64_applies_per_s": round(1e3 / gpu_f64_ms, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,10 +428,15 @@ def main():
     ap.add_argument("--max-inner", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--workload", choices=["headline", "batched", "warmstart"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "batched", "warmstart", "scattered"],
+                    default="headline",
                     help="headline: the 128x128x96x24 solve (default); batched: 256 uneven "
                          "3-D problems in one persistent launch vs the sequential loop; "
-                         "warmstart: the learned warm start on 64x64x64x16 blob problems")
+                         "warmstart: the learned warm start on 64x64x64x16 blob problems; "
+                         "scattered: the spline fit to 9M scattered sites, 128x128x128x16")
+    ap.add_argument("--sop-rtol", type=float, default=1e-5,
+                    help="relative residual target of the scattered-data solve")
+    ap.add_argument("--sop-max-iter", type=int, default=5000)
     ap.add_argument("--ws-seeds", type=int, default=8,
                     help="held-out seeds (from 10000) of the warm-start gain measurement")
     ap.add_argument("--no-warmstart", action="store_true",
@@ -363,6 +478,9 @@ def main():
 
     if args.workload == "batched":
         run_batched(args, cta, torch)
+        return
+    if args.workload == "scattered":
+        run_scattered(args, cta, torch)
         return
     if args.workload == "warmstart":
         ws = run_warmstart(args, cta, torch, list(range(10000, 10000 + args.ws_seeds)))

@@ -79,10 +79,10 @@ __device__ __forceinline__ void lds_add(T* p, T v) {
 
 // Acc[window] += v * (outer product of the weights)
 template <typename T, int N, int K>
-__device__ __forceinline__ void win_add(T* Acc, const T (&w)[4][4], const SopGeom& g, int off, T v) {
+__device__ __forceinline__ void win_add(double* Acc, const T (&w)[4][4], const SopGeom& g, int off, T v) {
     if constexpr (K == N - 1) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) lds_add(Acc + off + a, v * w[K][a]);
+        for (int a = 0; a < 4; ++a) lds_add(Acc + off + a, (double)(v * w[K][a]));
     } else {
 #pragma unroll
         for (int a = 0; a < 4; ++a) win_add<T, N, K + 1>(Acc, w, g, off + a * g.ts[K], v * w[K][a]);
@@ -102,9 +102,13 @@ __global__ __launch_bounds__(CTA_WG) void k_sop_brick(SopGeom g, const float* __
                                                       T* __restrict__ yout, T* __restrict__ tiles,
                                                       const CgScalars* scal) {
     if (scal && scal->done) return;
+    // LDS: the accumulator tile in FP64 (FP64 LDS atomics; also for FP32
+    // data, whose FP32 LDS atomics measured several times slower), then the
+    // coefficient tile in T
     extern __shared__ __align__(16) unsigned char sop_smem[];
-    T* Xs = reinterpret_cast<T*>(sop_smem);
-    T* Acc = MODE == SOP_NRM ? Xs + g.tile : Xs;
+    double* Acc = reinterpret_cast<double*>(sop_smem);
+    T* Xs = MODE == SOP_FWD ? reinterpret_cast<T*>(sop_smem)
+                            : reinterpret_cast<T*>(sop_smem + (size_t)g.tile * sizeof(double));
     const int chunk = blockIdx.x;
     // brick coordinates and the first cell / coefficient of the brick
     int b0[4] = {0, 0, 0, 0};
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(CTA_WG) void k_sop_brick(SopGeom g, const float* __
             }
             Xs[e] = ok ? X[gi] : (T)0;
         }
-        if constexpr (MODE != SOP_FWD) Acc[e] = (T)0;
+        if constexpr (MODE != SOP_FWD) Acc[e] = 0.0;
     }
     __syncthreads();
     const int lo = cstart[chunk], hi = cstart[chunk + 1];
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(CTA_WG) void k_sop_brick(SopGeom g, const float* __
     if constexpr (MODE != SOP_FWD) {
         __syncthreads();
         T* dst = tiles + (int64_t)chunk * g.tile;
-        for (int e = threadIdx.x; e < g.tile; e += CTA_WG) dst[e] = Acc[e];
+        for (int e = threadIdx.x; e < g.tile; e += CTA_WG) dst[e] = (T)Acc[e];
     }
 }
 
@@ -257,11 +261,16 @@ template <typename T, int N>
 hipError_t brick_T(int mode, const SopGeom& g, const float* coords, int64_t S, const int* perm,
                    const int* cstart, const int* cbrick, int nchunks, const void* X, const void* yin,
                    void* yout, void* tiles, const CgScalars* scal, hipStream_t s) {
-    const size_t lds = (size_t)g.tile * sizeof(T) * (mode == SOP_NRM ? 2 : 1);
+    const size_t lds = mode == SOP_FWD ? (size_t)g.tile * sizeof(T)
+                     : mode == SOP_ADJ ? (size_t)g.tile * sizeof(double)
+                                       : (size_t)g.tile * (sizeof(double) + sizeof(T));
     if (lds > 65536) {
-        // two FP64 tiles exceed the default 64 KB of dynamic LDS
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_sop_brick<T, N, SOP_NRM>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        // the accumulator and coefficient tiles exceed the default 64 KB of dynamic LDS
+        hipError_t e = mode == SOP_NRM
+            ? hipFuncSetAttribute(reinterpret_cast<const void*>(k_sop_brick<T, N, SOP_NRM>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+            : hipFuncSetAttribute(reinterpret_cast<const void*>(k_sop_brick<T, N, SOP_ADJ>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     if (mode == SOP_FWD)
