@@ -39,6 +39,7 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # copy-kernel calibration of the rocprofv3 FETCH_SIZE / WRITE_SIZE counters and the
 # traffic of the dominant kernel, both from profiles/ (None until measured)
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_headline_kernels_128x128x96x24.json")
+SOP_TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_scattered_kernels_128x128x128x16_9M.json")
 # trained warm-start network of the 64x64x64x16 blob workload
 WS_CKPT = os.path.join(HERE, "paper_1001_5460_amd", "weights", "ws_64x64x64x16.npz")
 
@@ -370,8 +371,18 @@ def run_scattered(args, cta, torch):
     brick = kern.get("sop_brick.f32", {"avg_ms": float("nan")})
     lds_bytes = S * win * (4 + 8)
     achieved = lds_bytes / (brick["avg_ms"] * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(SOP_TRAFFIC_FILE):
+        try:
+            with open(SOP_TRAFFIC_FILE) as f:
+                ent = json.load(f).get("kernels", {}).get("sop_brick.f32")
+            # HBM bytes from the counters, while the kernel sources are the measured ones
+            if ent is not None and ent.get("sources") == kernel_sources_digest():
+                traffic = ent.get("traffic_bytes_per_launch")
+        except Exception:
+            traffic = None
     roof = {"bound": "lds", "kernel": "sop_brick.f32", "achieved": round(achieved, 1), "peak": 78643.2,
-            "unit": "GB/s", "frac": round(achieved / 78643.2, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / 78643.2, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": lds_bytes, "avg_launch_ms": brick["avg_ms"]}
     out = {
         "metric": f"time to {rtol:g} relative residual, scattered-data spline fit (FP32 CG)",
