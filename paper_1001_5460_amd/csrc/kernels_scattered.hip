@@ -175,67 +175,129 @@ __global__ __launch_bounds__(CTA_WG) void k_sop_brick(SopGeom g, const float* __
     }
 }
 
-// Q[c] = sum of the tile slots covering c (bricks in row-major order, chunks
-// in order) + lam * sum_k (R_k along mode k)(P)[c]; FP64 partials of <P, Q>.
+// Q[c] = sum of the tile slots covering c + lam * sum_k (R_k along mode k)(P)[c];
+// FP64 partials of <P, Q>.  Workgroups walk the bricks; brick b owns the
+// coefficients [b_k bc_k, (b_k + 1) bc_k) per mode (the last brick of a mode
+// up to n_k).  An owned coefficient at local offset l_k is also covered by the
+// tiles of bricks b_k - j with l_k + j bc_k <= bc_k + 2.  When every bc_k >= 3
+// only j in {0, 1} occurs: the chunk ranges of those 2^N bricks are read into
+// LDS once per brick, and the 2^N combinations are unrolled so that their
+// tile loads issue together; the sum runs over the combinations in a fixed
+// order and over each brick's chunks in order.
 template <typename T, int N>
 __global__ __launch_bounds__(CTA_WG) void k_sop_gather(SopGeom g, const T* __restrict__ tiles,
                                                        const int* __restrict__ bchunk0,
                                                        const T* __restrict__ P, const T* __restrict__ rb,
                                                        T lam, T* __restrict__ Q, double* partials,
-                                                       const CgScalars* scal) {
+                                                       int nbricks, const CgScalars* scal) {
     if (scal && scal->done) return;
     __shared__ double red[4];
+    __shared__ int nbr_lo[16], nbr_hi[16];
+    bool wide = true;
+#pragma unroll
+    for (int k = 0; k < N; ++k) wide = wide && g.bc[k] >= 3;
     double dot = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * CTA_WG + threadIdx.x; c < g.ncoef;
-         c += (int64_t)gridDim.x * CTA_WG) {
-        int ck[4] = {0, 0, 0, 0}, blo[4] = {0, 0, 0, 0}, bhi[4] = {0, 0, 0, 0}, b[4];
+    for (int brick = blockIdx.x; brick < nbricks; brick += gridDim.x) {
+        int bk[4] = {0, 0, 0, 0}, ob[4] = {1, 1, 1, 1}, bs[4] = {0, 0, 0, 0};
+        int owned = 1;
         {
-            int64_t rem = c;
+            int rem = brick, st = 1;
 #pragma unroll
             for (int k = N - 1; k >= 0; --k) {
-                ck[k] = (int)(rem % g.n[k]);
-                rem /= g.n[k];
+                bk[k] = rem % g.nb[k];
+                rem /= g.nb[k];
+                bs[k] = st;
+                st *= g.nb[k];
+                ob[k] = bk[k] == g.nb[k] - 1 ? g.n[k] - bk[k] * g.bc[k] : g.bc[k];
+                owned *= ob[k];
             }
         }
+        if (wide) {
+            __syncthreads();  // the previous brick's ranges are no longer read
+            if ((int)threadIdx.x < (1 << N)) {
+                int br = brick;
+                bool ok = true;
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            blo[k] = ck[k] < 3 ? 0 : (ck[k] - 3) / g.bc[k];
-            bhi[k] = min(g.nb[k] - 1, ck[k] / g.bc[k]);
-            b[k] = blo[k];
-        }
-        T sum = (T)0;
-        for (;;) {
-            int brick = 0, local = 0;
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                brick = brick * g.nb[k] + b[k];
-                local += (ck[k] - b[k] * g.bc[k]) * g.ts[k];
+                for (int k = 0; k < N; ++k) {
+                    const int jk = ((int)threadIdx.x >> k) & 1;
+                    ok = ok && bk[k] - jk >= 0;
+                    br -= jk * bs[k];
+                }
+                nbr_lo[threadIdx.x] = ok ? bchunk0[br] : 0;
+                nbr_hi[threadIdx.x] = ok ? bchunk0[br + 1] : 0;
             }
-            const int c1 = bchunk0[brick + 1];
-            for (int ch = bchunk0[brick]; ch < c1; ++ch) sum += tiles[(int64_t)ch * g.tile + local];
-            int k = N - 1;
-            for (; k >= 0; --k) {
-                if (++b[k] <= bhi[k]) break;
-                b[k] = blo[k];
-            }
-            if (k < 0) break;
+            __syncthreads();
         }
-        if (P) {
-            T reg = (T)0;
+        for (int e = threadIdx.x; e < owned; e += CTA_WG) {
+            int l[4] = {0, 0, 0, 0}, jm[4] = {0, 0, 0, 0}, j[4];
+            int64_t c = 0;
+            {
+                int rem = e;
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const T* row = rb + 5 * ((int64_t)g.roff[k] + ck[k]);
-#pragma unroll
-                for (int d = -2; d <= 2; ++d) {
-                    const int j = ck[k] + d;
-                    if (j >= 0 && j < g.n[k]) reg += row[d + 2] * P[c + (int64_t)d * g.gs[k]];
+                for (int k = N - 1; k >= 0; --k) {
+                    l[k] = rem % ob[k];
+                    rem /= ob[k];
+                    c += (int64_t)(bk[k] * g.bc[k] + l[k]) * g.gs[k];
+                    while (bk[k] - jm[k] - 1 >= 0 && l[k] + (jm[k] + 1) * g.bc[k] <= g.bc[k] + 2) ++jm[k];
+                    j[k] = jm[k];
                 }
             }
-            const T q = sum + lam * reg;
-            Q[c] = q;
-            dot += (double)P[c] * (double)q;
-        } else {
-            Q[c] = sum;
+            T sum = (T)0;
+            if (wide) {
+                int base = 0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) base += l[k] * g.ts[k];
+#pragma unroll
+                for (int q = 0; q < (1 << N); ++q) {
+                    bool cov = true;
+                    int local = base;
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        const int jk = (q >> k) & 1;
+                        cov = cov && jk <= jm[k];
+                        local += jk * g.bc[k] * g.ts[k];
+                    }
+                    if (cov) {
+                        const int c1 = nbr_hi[q];
+                        for (int ch = nbr_lo[q]; ch < c1; ++ch) sum += tiles[(int64_t)ch * g.tile + local];
+                    }
+                }
+            } else {
+                for (;;) {
+                    int br = brick, local = 0;
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        br -= j[k] * bs[k];
+                        local += (l[k] + j[k] * g.bc[k]) * g.ts[k];
+                    }
+                    const int c1 = bchunk0[br + 1];
+                    for (int ch = bchunk0[br]; ch < c1; ++ch) sum += tiles[(int64_t)ch * g.tile + local];
+                    int k = N - 1;
+                    for (; k >= 0; --k) {
+                        if (--j[k] >= 0) break;
+                        j[k] = jm[k];
+                    }
+                    if (k < 0) break;
+                }
+            }
+            if (P) {
+                T reg = (T)0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const int ck = bk[k] * g.bc[k] + l[k];
+                    const T* row = rb + 5 * ((int64_t)g.roff[k] + ck);
+#pragma unroll
+                    for (int d = -2; d <= 2; ++d) {
+                        const int jj = ck + d;
+                        if (jj >= 0 && jj < g.n[k]) reg += row[d + 2] * P[c + (int64_t)d * g.gs[k]];
+                    }
+                }
+                const T q = sum + lam * reg;
+                Q[c] = q;
+                dot += (double)P[c] * (double)q;
+            } else {
+                Q[c] = sum;
+            }
         }
     }
     if (partials) block_partial(dot, partials, red);
@@ -300,18 +362,19 @@ hipError_t brick_N(int mode, const SopGeom& g, const float* coords, int64_t S, c
 template <typename T>
 hipError_t gather_N(const SopGeom& g, const void* tiles, const int* bchunk0, const void* P, const void* rb,
                     double lam, void* Q, double* partials, const CgScalars* scal, int grid, hipStream_t s) {
+    const int nbricks = g.nb[0] * (g.N > 1 ? g.nb[1] : 1) * (g.N > 2 ? g.nb[2] : 1) * (g.N > 3 ? g.nb[3] : 1);
     switch (g.N) {
         case 2:
             k_sop_gather<T, 2><<<grid, CTA_WG, 0, s>>>(g, (const T*)tiles, bchunk0, (const T*)P, (const T*)rb,
-                                                      (T)lam, (T*)Q, partials, scal);
+                                                      (T)lam, (T*)Q, partials, nbricks, scal);
             break;
         case 3:
             k_sop_gather<T, 3><<<grid, CTA_WG, 0, s>>>(g, (const T*)tiles, bchunk0, (const T*)P, (const T*)rb,
-                                                      (T)lam, (T*)Q, partials, scal);
+                                                      (T)lam, (T*)Q, partials, nbricks, scal);
             break;
         case 4:
             k_sop_gather<T, 4><<<grid, CTA_WG, 0, s>>>(g, (const T*)tiles, bchunk0, (const T*)P, (const T*)rb,
-                                                      (T)lam, (T*)Q, partials, scal);
+                                                      (T)lam, (T*)Q, partials, nbricks, scal);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -336,8 +399,9 @@ hipError_t launch_sop_brick(int dt, int mode, const SopGeom& g, const float* coo
 hipError_t launch_sop_gather(int dt, const SopGeom& g, const void* tiles, const int* bchunk0, const void* P,
                              const void* rb, double lam, void* Q, double* partials, CgScalars* scal, int post,
                              double* out, hipStream_t s) {
-    const int64_t per = (int64_t)CTA_WG * 4;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((g.ncoef + per - 1) / per, kMaxGrid));
+    int64_t nbr = 1;
+    for (int k = 0; k < g.N; ++k) nbr *= g.nb[k];
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nbr, kMaxGrid));
     {
         ProfScope ps(dt == DT_F64 ? "sop_gather.f64" : "sop_gather.f32", s);
         hipError_t e = dt == DT_F64 ? gather_N<double>(g, tiles, bchunk0, P, rb, lam, Q, partials, scal, grid, s)
