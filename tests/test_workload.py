@@ -63,3 +63,27 @@ def test_blob_field_torch_deterministic_and_shaped():
     M = Xn.double().reshape(6, -1).numpy()
     assert np.linalg.matrix_rank(M, tol=1e-6 * np.abs(M).max()) <= 8
     assert float(Xn.abs().max()) <= 8 * 2.0 + 1e-6
+
+
+def test_scattered_sites_seeded_and_in_range():
+    import workload
+    a = workload.scattered_sites(4, 5000, seed=9, clustered=0.4)
+    b = workload.scattered_sites(4, 5000, seed=9, clustered=0.4)
+    assert a.dtype == np.float32 and a.shape == (4, 5000)
+    assert np.array_equal(a, b)
+    assert a.min() >= 0.0 and a.max() <= 1.0
+    e = workload.with_endpoints(a)
+    for s in range(16):
+        for k in range(4):
+            assert e[k, s] == (1.0 if (s >> k) & 1 else 0.0)
+    assert np.array_equal(e[:, 16:], a[:, 16:])
+
+
+def test_scattered_config_shapes():
+    import workload
+    p = workload.scattered_config(scale=8)
+    assert p.n == (16, 16, 16, 4) and p.coords.shape[0] == 4
+    assert p.X_true.shape == p.n and p.noise.shape == (p.count,)
+    assert p.count == int(9_000_000 * np.prod(p.n) / (128 * 128 * 128 * 16))
+    full = workload.SCATTERED
+    assert full["n"] == (128, 128, 128, 16) and full["count"] == 9_000_000
