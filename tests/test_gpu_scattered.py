@@ -174,3 +174,29 @@ def test_application_size_sampled():
             coef *= np.where(ok, wk[np.arange(sel.size), np.clip(off, 0, 3)], 0.0)
         want_c = float(coef @ fs) + regX[c]
         assert abs(Q[c] - want_c) <= 1e-12 * max(1.0, abs(want_c)), (c, Q[c], want_c)
+
+
+def test_cg_iteration_limit_reports_not_converged():
+    torch = torch_cuda()
+    n = (12, 10, 9, 8)
+    p = workload.scattered_problem(n, 4000, 1e-3, 0.01, seed=41, rtol=1e-10)
+    ref = sc.ScatteredOperator(p.coords, n, p.D, p.lam)
+    B = ref.rhs(ref.forward(p.X_true) + p.noise)
+    op = cta.ScatteredOperator(p.coords, n, p.D, p.lam)
+    X, info = op.solve(dev(B, torch.float64), rtol=1e-12, max_iter=3, check_every=2)
+    assert info["status"] == cta.CTA_NOT_CONVERGED and info["iters"] == 3, info
+    # three CG steps from zero: the same iterate as the oracle's three steps
+    ocg = oracle.cg(ref, B, rtol=0.0, max_iter=3, restart=False)
+    assert rel_fro(host(X), ocg.x) <= 1e-12
+
+
+def test_repeated_applies_agree_to_rounding():
+    """The order of the LDS additions inside a tile is not fixed: two applies
+    may differ by rounding only."""
+    torch = torch_cuda()
+    p = _problem((24, 20, 16, 12), 40000, 0.5, 1e-3)
+    op = cta.ScatteredOperator(p.coords, p.n, p.D, p.lam)
+    X = dev(np.random.default_rng(8).standard_normal(p.n), torch.float64)
+    Q1 = host(op.apply(X))
+    Q2 = host(op.apply(X))
+    assert rel_fro(Q1, Q2) <= 1e-14
