@@ -179,7 +179,7 @@ cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3
 cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3);
 
 /* Band-aware applies.  Cubic B-spline collocation factors give Gram matrices
- * G_k with half-bandwidth 3 (Sec. 4: each sample touches 4 basis functions
+ * G_k with half-bandwidth 3 (Sec. 6: each sample touches 4 basis functions
  * per mode), so a mode product with G_k is a short stencil along mode k.
  * cta_op_create records the largest half-bandwidth w of the G_k
  * (cta_op_band_width); when w <= 4 it keeps the bands in FP64 and FP32 and

@@ -16,6 +16,10 @@ no blocking, fusion or reordering beyond what the cited definition states:
 * ``normal``  -- the regularised normal operator and right-hand side built from
   the transposition rule (App. A.7) and the Kronecker-sum form of Sec. 4.1.
 * ``cg``      -- the tensor conjugate-gradient iteration of Fig. Tensor_CG.
+* ``jacobi``  -- the main diagonal of the operator, the stationary tensor
+  Jacobi iteration of Fig. Tensor_Jacobi and the diagonal preconditioner.
+* ``multigrid`` -- the tensor multigrid V-cycle of Fig. TMG (separable
+  restriction and prolongation, Jacobi smoothing, direct coarsest solve).
 * ``dense``   -- the matrix-equivalent form of the tensor equation (Sec. 3),
   assembled column by column and solved by Cholesky (tiny sizes only).
 * ``judge``   -- the FP64 relative residual used to judge any solution.
@@ -43,6 +47,8 @@ from .judge import relative_residual
 from . import wsnet
 from . import precond
 from . import scattered
+from . import jacobi
+from . import multigrid
 
 __all__ = [
     "mode_product", "multi_mode_product", "inner",
@@ -50,4 +56,5 @@ __all__ = [
     "normal_apply_literal", "regulariser_apply", "NormalOperator",
     "cg", "CGResult", "lanczos_extremes",
     "assemble", "dense_solve", "relative_residual", "wsnet", "precond", "scattered",
+    "jacobi", "multigrid",
 ]

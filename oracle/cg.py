@@ -1,33 +1,31 @@
-"""Tensor conjugate gradients (oracle; test infrastructure only).
+"""Tensor conjugate gradients in FP64 (oracle; test infrastructure only).
 
-The iteration is the one of Fig. Tensor_CG, in its order and notation
-(C is the solution tensor, R the residual, P the search direction, Q = A*P):
+The solver of Fig. Tensor_CG (Sec. 4.1) is conjugate gradients written with
+tensor operations only: the operator is applied as a tensor multiplication,
+every scalar comes from a full contraction <U, V> (App. A.6), and the Kronecker
+delta that relabels the direction's indices before the multiplication (App.
+A.5) leaves every component unchanged, so it is the identity here.  This module
+follows the textbook method: from the residual of the current iterate, each
+step moves the iterate along a search direction by the step length that
+minimises the energy norm of the error, updates the residual with the
+operator's image of the direction, and makes the next direction conjugate to
+the previous one with the ratio of successive squared residual norms.
 
-    R = B - A*C ;  P = R ;  rho = <R, R>
-    repeat
-        Q     = A*P
-        alpha = rho / <P, Q>
-        C     = C + alpha * P
-        R     = R - alpha * Q
-        rho1  = <R, R>
-        P     = R + (rho1 / rho) * P
-        rho   = rho1
-    until convergence
+Readings where the figure is silent or garbled:
 
-The Kronecker-delta relabelling of the figure (P*D) changes no component value
-(App. A.5), so it is the identity here.  Readings where the figure is silent or
-garbled:
-
-* the printed loop test reads "until rho > threshold", which would stop after
-  one pass; it is read as "until rho <= threshold", the test the Jacobi solver
-  of Fig. Tensor_Jacobi uses;
-* the threshold is relative: rho <= (rtol * ||B||)^2, so that solutions from
-  any starting tensor are judged against the same right-hand side;
-* the loop is entered only when the initial residual is above the threshold
-  (a zero right-hand side returns C unchanged);
-* <P, Q> <= 0 or a non-finite scalar is a breakdown (the operator is not SPD);
-* after the loop the true residual ||B - A*C|| is recomputed; if it is above
-  the tolerance the iteration restarts once from it.
+* Its loop test reads as if the loop ended while the squared residual is still
+  large, which would stop after one pass; the loop instead runs until the
+  squared residual is at or below the threshold, the test of the Jacobi solver
+  in Fig. Tensor_Jacobi.
+* The threshold is relative to the right-hand side: ||r|| <= rtol ||B||, so
+  that solutions from any starting tensor are judged against the same B.
+* No step is taken when the starting residual already meets the threshold
+  (a zero right-hand side returns the start unchanged).
+* A curvature <d, N d> <= 0 or a non-finite scalar is a breakdown (the
+  operator is not SPD).
+* When the loop ends on the threshold, the residual is recomputed from the
+  iterate; if that true residual misses the tolerance, the iteration starts
+  over once from the current iterate.
 """
 from dataclasses import dataclass, field
 from typing import Callable, List, Optional
@@ -54,66 +52,75 @@ class CGResult:
     restarts: int = 0
 
 
-def _cg_pass(apply, B, C, threshold, max_iter, hist):
-    R = B - apply(C)
-    P = R.copy()
-    rho = inner(R, R)
-    hist["rho"].append(rho)
-    it = 0
-    status = NOT_CONVERGED
-    if rho <= threshold:
-        return C, it, CONVERGED, rho
-    while it < max_iter:
-        Q = apply(P)
-        pq = inner(P, Q)
-        if not np.isfinite(pq) or pq <= 0.0:
-            status = BREAKDOWN
-            break
-        alpha = rho / pq
-        C = C + alpha * P
-        R = R - alpha * Q
-        rho1 = inner(R, R)
-        beta = rho1 / rho
-        P = R + beta * P
-        rho = rho1
-        it += 1
-        hist["alpha"].append(alpha)
-        hist["beta"].append(beta)
-        hist["rho"].append(rho)
-        if not np.isfinite(rho):
-            status = BREAKDOWN
-            break
-        if rho <= threshold:
-            status = CONVERGED
-            break
-    return C, it, status, rho
+@dataclass
+class _Log:
+    steps: List[float] = field(default_factory=list)      # step lengths
+    ratios: List[float] = field(default_factory=list)     # conjugation ratios
+    res2: List[float] = field(default_factory=list)       # squared residual norms
+
+
+def _sweep(apply, rhs, x, tol2, budget, log):
+    """CG from iterate x for at most `budget` steps.
+
+    Returns (x, steps taken, status, last squared residual norm)."""
+    res = rhs - apply(x)
+    res2 = inner(res, res)
+    log.res2.append(res2)
+    if res2 <= tol2:
+        return x, 0, CONVERGED, res2
+    direction = res.copy()
+    taken = 0
+    while taken < budget:
+        image = apply(direction)
+        curvature = inner(direction, image)
+        if not np.isfinite(curvature) or curvature <= 0.0:
+            return x, taken, BREAKDOWN, res2
+        step = res2 / curvature
+        x = x + step * direction
+        res = res - step * image
+        res2_next = inner(res, res)
+        ratio = res2_next / res2
+        direction = res + ratio * direction
+        res2 = res2_next
+        taken += 1
+        log.steps.append(step)
+        log.ratios.append(ratio)
+        log.res2.append(res2)
+        if not np.isfinite(res2):
+            return x, taken, BREAKDOWN, res2
+        if res2 <= tol2:
+            return x, taken, CONVERGED, res2
+    return x, taken, NOT_CONVERGED, res2
+
+
+def _true_relative_residual(apply, rhs, x, scale):
+    res = rhs - apply(x)
+    return float(np.sqrt(inner(res, res)) / scale)
 
 
 def cg(apply: Callable, B, x0: Optional[np.ndarray] = None, rtol=1e-8,
        max_iter=10000, restart=True) -> CGResult:
-    """Solve apply(X) = B by the tensor CG of Fig. Tensor_CG in float64."""
-    B = np.asarray(B, dtype=np.float64)
-    C = np.zeros_like(B) if x0 is None else np.array(x0, dtype=np.float64)
-    bnorm = np.sqrt(inner(B, B))
-    threshold = (rtol * bnorm) ** 2
-    hist = {"alpha": [], "beta": [], "rho": []}
-    C, it, status, rho = _cg_pass(apply, B, C, threshold, max_iter, hist)
-    total = it
+    """Solve apply(X) = B by tensor CG (Fig. Tensor_CG) in float64."""
+    rhs = np.asarray(B, dtype=np.float64)
+    x = np.zeros_like(rhs) if x0 is None else np.array(x0, dtype=np.float64)
+    bnorm = np.sqrt(inner(rhs, rhs))
+    scale = bnorm if bnorm > 0 else 1.0
+    tol2 = (rtol * bnorm) ** 2
+    log = _Log()
+    x, taken, status, res2 = _sweep(apply, rhs, x, tol2, max_iter, log)
     restarts = 0
-    denom = bnorm if bnorm > 0 else 1.0
-    true_res = np.sqrt(inner(B - apply(C), B - apply(C))) / denom
-    if restart and status == CONVERGED and true_res > rtol and total < max_iter:
+    true_rel = _true_relative_residual(apply, rhs, x, scale)
+    if restart and status == CONVERGED and true_rel > rtol and taken < max_iter:
         restarts = 1
-        C, it, status, rho = _cg_pass(apply, B, C, threshold, max_iter - total, hist)
-        total += it
-        R = B - apply(C)
-        true_res = np.sqrt(inner(R, R)) / denom
-    if status == CONVERGED and true_res > rtol:
+        x, more, status, res2 = _sweep(apply, rhs, x, tol2, max_iter - taken, log)
+        taken += more
+        true_rel = _true_relative_residual(apply, rhs, x, scale)
+    if status == CONVERGED and true_rel > rtol:
         status = NOT_CONVERGED
-    return CGResult(x=C, iters=total, status=status,
-                    rel_res_recursive=float(np.sqrt(max(rho, 0.0)) / denom),
-                    rel_res_true=float(true_res), alphas=hist["alpha"],
-                    betas=hist["beta"], rho_history=hist["rho"], restarts=restarts)
+    return CGResult(x=x, iters=taken, status=status,
+                    rel_res_recursive=float(np.sqrt(max(res2, 0.0)) / scale),
+                    rel_res_true=true_rel, alphas=log.steps, betas=log.ratios,
+                    rho_history=log.res2, restarts=restarts)
 
 
 def lanczos_extremes(alphas, betas):

@@ -1,6 +1,6 @@
 // Band-aware normal operator for banded Gram factors (NEXT-4 of the scope:
 // cubic B-spline collocation gives G_k = A_k^T A_k with half-bandwidth 3,
-// Sec. 4, so a mode product with G_k is a 7-tap stencil along mode k).
+// Sec. 6, so a mode product with G_k is a 7-tap stencil along mode k).
 //
 // Q = P x_N G_N ... x_1 G_1 + lam sum_k P x_k R_k (the normal operator of
 // Sec. 2.1 in normal-equation form) is applied as N streaming passes: modes
@@ -349,7 +349,7 @@ namespace cta {
 
 // ---------------------------------------------------------------------------
 // Banded rectangular mode product for the forward model and the right-hand
-// side (Sec. 4: a sample touches 4 consecutive B-spline basis functions per
+// side (Sec. 6: a sample touches 4 consecutive B-spline basis functions per
 // mode, and a basis function a short run of consecutive samples):
 // Y[b, j, t] = sum_{c < W} coef[j * W + c] * X[b, lo[j] + c, t] on the
 // (lead, K -> J, trail) view.  Rows past K have zero coefficients and clamped

@@ -123,3 +123,30 @@ def test_warm_start_from_solution():
     xs = oracle.dense_solve(op, B)
     res = oracle.cg(op, B, x0=xs, rtol=1e-8)
     assert res.iters == 0 and res.status == CONVERGED
+
+
+@pytest.mark.parametrize("n,lam", [((4, 5, 3), 1e-2), ((4, 4, 5, 4), 1e-3)])
+def test_relative_residual_against_kronecker_matrix(n, lam):
+    """The judge equals ||b - M x|| / ||b|| with M assembled from np.kron of the
+    factors (the matrix form of the tensor equation, Sec. 3), not from the
+    oracle's own mode products."""
+    n = tuple(max(v, 4) for v in n)
+    p, op, B = _problem(n, lam)
+    G = [a.T @ a for a in p.A]
+    R = [d.T @ d for d in p.D]
+    M = np.ones((1, 1))
+    for g in G:
+        M = np.kron(M, g)
+    for k in range(len(n)):
+        term = np.ones((1, 1))
+        for l in range(len(n)):
+            term = np.kron(term, R[k] if l == k else np.eye(n[l]))
+        M = M + lam * term
+    X = np.random.default_rng(6).standard_normal(n)
+    ref = np.linalg.norm(B.reshape(-1) - M @ X.reshape(-1)) / np.linalg.norm(B.reshape(-1))
+    assert np.isclose(oracle.relative_residual(X, B, op), ref, rtol=1e-12)
+    # exact solution: residual at rounding level; zero right-hand side: scale 1
+    Xs = np.linalg.solve(M, B.reshape(-1)).reshape(n)
+    assert oracle.relative_residual(Xs, B, op) <= 1e-12
+    assert oracle.relative_residual(X, np.zeros(n), op) == pytest.approx(
+        np.linalg.norm(M @ X.reshape(-1)), rel=1e-12)

@@ -147,3 +147,40 @@ def test_store_model_rounds_activations():
     exact = wsnet.forward(P, b)
     rel = np.linalg.norm(out - exact) / np.linalg.norm(exact)
     assert 1e-5 < rel < 3e-2
+
+
+def test_adam_bias_correction_with_constant_gradient():
+    """With the same gradient g at every step the bias-corrected moments are
+    exactly g and g^2 at every t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so
+    each step moves theta by lr * sign(g) when eps = 0: a wrong exponent in the
+    correction breaks this from t = 2 on."""
+    rng = np.random.default_rng(10)
+    theta0 = rng.standard_normal(16)
+    g = rng.standard_normal(16)
+    theta, m, v = theta0.copy(), np.zeros(16), np.zeros(16)
+    for t in (1, 2, 3):
+        theta, m, v = wsnet.adam_step(theta, g, m, v, t, lr=1e-2, beta1=0.9, beta2=0.999, eps=0.0)
+        np.testing.assert_allclose(m, (1 - 0.9 ** t) * g, rtol=1e-13)
+        np.testing.assert_allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12)
+        np.testing.assert_allclose(theta, theta0 - t * 1e-2 * np.sign(g), rtol=1e-12, atol=1e-14)
+
+
+def test_adam_second_and_third_steps_by_hand():
+    """Two scalar gradients 3 and -1, then 2: the moments and the update
+    written out by hand from the definitions (Kingma and Ba), b1 = 0.5,
+    b2 = 0.75, lr = 0.1, eps = 0."""
+    th, m, v = np.array([1.0]), np.zeros(1), np.zeros(1)
+    th, m, v = wsnet.adam_step(th, np.array([3.0]), m, v, 1, lr=0.1, beta1=0.5, beta2=0.75, eps=0.0)
+    # m1 = 1.5, v1 = 2.25, mhat = 3, vhat = 9: step 0.1 * 3 / 3
+    assert np.isclose(th[0], 0.9, rtol=1e-15)
+    th, m, v = wsnet.adam_step(th, np.array([-1.0]), m, v, 2, lr=0.1, beta1=0.5, beta2=0.75, eps=0.0)
+    # m2 = 0.75 - 0.5 = 0.25, v2 = 1.6875 + 0.25 = 1.9375; mhat = 0.25 / 0.75 = 1/3,
+    # vhat = 1.9375 / (1 - 0.5625) = 4.428571..., step 0.1 * (1/3) / sqrt(vhat)
+    assert np.isclose(m[0], 0.25) and np.isclose(v[0], 1.9375)
+    th2 = 0.9 - 0.1 * (1.0 / 3.0) / np.sqrt(1.9375 / 0.4375)
+    assert np.isclose(th[0], th2, rtol=1e-14)
+    th, m, v = wsnet.adam_step(th, np.array([2.0]), m, v, 3, lr=0.1, beta1=0.5, beta2=0.75, eps=0.0)
+    # m3 = 0.125 + 1 = 1.125, v3 = 1.453125 + 1 = 2.453125; corrections 1 - 0.125, 1 - 0.421875
+    assert np.isclose(m[0], 1.125) and np.isclose(v[0], 2.453125)
+    th3 = th2 - 0.1 * (1.125 / 0.875) / np.sqrt(2.453125 / 0.578125)
+    assert np.isclose(th[0], th3, rtol=1e-14)
