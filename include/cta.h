@@ -246,11 +246,14 @@ typedef struct {
                            (reliable updates: the first read of a group after as many
                            iterations as the previous group took, then every
                            max(1, check_every / 4)) */
-    int precond;        /* 1: preconditioned CG with the operator's tensor-inverse
-                           preconditioner (cta_op_set_preconditioner); the
+    int precond;        /* preconditioned CG (not for cta_solve_batched): the
                            iteration uses z = M^-1 r for the search direction and
                            <r, z> for the step lengths, the stopping test stays
-                           ||r|| <= rtol ||B|| (not for cta_solve_batched) */
+                           ||r|| <= rtol ||B||.  0: none; 1: the tensor-inverse
+                           preconditioner (cta_op_set_preconditioner); 2: the
+                           diagonal of N (tensor Jacobi, Fig. Tensor_Jacobi);
+                           3: one tensor multigrid V-cycle (Fig. TMG,
+                           cta_op_set_multigrid) */
 } cta_cg_opts;
 
 typedef struct {
@@ -276,6 +279,77 @@ cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype dtype,
 cta_status cta_tune_preconditioner(cta_op op, const void* B, void* X, cta_dtype dtype,
                                    const cta_cg_opts* opts, const double* host_c, int count,
                                    double* best_c, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Tensor Jacobi (Fig. Tensor_Jacobi, Sec. 4.1).  The main diagonal of N at
+ * multi-index i is d[i] = prod_k G_k[i_k, i_k] + lambda sum_k R_k[i_k, i_k]
+ * (the diagonal of a Kronecker product is the product of the factors'
+ * diagonals, and a Kronecker-sum term contributes R_k's diagonal); the
+ * handle keeps the per-mode diagonals and forms d on the fly, never as a
+ * tensor.  Flat tensor sizes must stay below 2^31.
+ *
+ * cta_apply_jacobi: Z = omega * R / d elementwise (R, Z device tensors of
+ * extents n, both F64 or both F32); optional FP64 <R, Z> to the device
+ * double *dot.  Asynchronous.
+ *
+ * cta_jacobi_solve: the stationary iteration of Fig. Tensor_Jacobi,
+ * U <- U + omega (B - N U) / d, from U = 0 (or X when opts->x0_given) until
+ * ||B - N U|| <= rtol ||B|| (tested before every sweep, as the figure's loop
+ * does) or opts->max_iter sweeps.  The printed iteration is omega = 1; it
+ * converges only when 2 diag(N) - N is positive definite, which Gram products
+ * of B-spline collocation are not, so omega < 2 / lambda_max(diag(N)^-1 N)
+ * is needed there (a diverging iteration ends with CTA_ERR_BREAKDOWN once the
+ * residual is not finite, or CTA_NOT_CONVERGED).  opts: precision
+ * CTA_PREC_F64 (B, X F64) or CTA_PREC_F32 (B, X F32), rtol, max_iter,
+ * x0_given, check_every; info->iters counts sweeps, rel_res_recursive is the
+ * last tested residual, rel_res_true the FP64 recomputation.  Synchronises
+ * `stream`.
+ * ---------------------------------------------------------------------- */
+cta_status cta_apply_jacobi(cta_op op, const void* R, void* Z, cta_dtype dtype, double omega, double* dot,
+                            void* stream);
+cta_status cta_jacobi_solve(cta_op op, const void* B, void* X, cta_dtype dtype, const cta_cg_opts* opts,
+                            double omega, cta_cg_info* host_info, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Tensor multigrid (Fig. TMG, Sec. 4.2): a V-cycle over a hierarchy of
+ * scales with separable restriction and prolongation (one matrix per mode),
+ * damped-Jacobi smoothing and a direct solve on the last scale, used as a CG
+ * preconditioner (cta_cg_opts.precond = 3) or applied alone.
+ *
+ * cta_op_set_multigrid builds the hierarchy (GetScale) on the host in FP64:
+ *  - mode k of a scale is coarsened to ceil(n_k / 2) while n_k >= 8 (else
+ *    kept); prolongation P_k (n_k x nc_k) is linear interpolation from nc_k
+ *    uniform points over the same index interval, restriction is P_k^T;
+ *  - the next scale's operator has the same form: G_k' = P_k^T G_k P_k (the
+ *    exact Galerkin image of the data term) and R_k' = s_k^2 P_k^T R_k P_k
+ *    with s_k^2 = prod_{l != k} n_l / nc_l (the regulariser's identity
+ *    factors become P_l^T P_l, lumped to (n_l / nc_l) I);
+ *  - scales are added while the current one has more than coarse_max
+ *    unknowns and a mode can be coarsened, up to max_levels scales in all;
+ *    the last one must have at most 4096 unknowns (CTA_ERR_ARG otherwise);
+ *  - every scale but the last is smoothed by nu sweeps of damped Jacobi
+ *    before and after the coarse-grid correction, with omega = omega_scale /
+ *    b and b = max(prod_k lmax(g_k^-1/2 G_k g_k^-1/2), max_k lmax(r_k^-1/2
+ *    R_k r_k^-1/2)) >= lambda_max(diag(N)^-1 N) (g_k, r_k the diagonals of
+ *    G_k, R_k); omega_scale in (0, 2);
+ *  - the last scale is solved with the inverse of its assembled matrix.
+ * max_levels < 2 removes the hierarchy.  The handle owns the coarse scales'
+ * operators, transfer matrices and vectors.  Synchronous.
+ *
+ * cta_op_multigrid_info: number of scales to *host_levels; for the first
+ * `capacity` scales their extents (user order, row-major [scale][mode]) and
+ * smoother weights omega (either array may be NULL).
+ *
+ * cta_apply_multigrid: Z = V(R), one V-cycle from zero on R, in `chain`
+ * precision (F64 tensors for CTA_PREC_F64, F32 for CTA_PREC_F32 and
+ * CTA_PREC_BF16); optional FP64 <R, Z> to the device double *dot.
+ * Asynchronous; uses the handle's work vectors (not reentrant per handle).
+ * ---------------------------------------------------------------------- */
+cta_status cta_op_set_multigrid(cta_op op, int max_levels, int64_t coarse_max, int nu, double omega_scale);
+cta_status cta_op_multigrid_info(cta_op op, int* host_levels, int64_t* host_extents, double* host_omega,
+                                 int capacity);
+cta_status cta_apply_multigrid(cta_op op, const void* R, void* Z, cta_dtype dtype, cta_precision chain,
+                               double* dot, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched solve: `count` independent problems of order 3 in one persistent

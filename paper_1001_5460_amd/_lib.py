@@ -110,6 +110,13 @@ _SIGS = {
     "cta_sop_apply_normal": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P]),
     "cta_sop_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                         ctypes.c_int, ctypes.POINTER(_CgInfo), _P]),
+    "cta_apply_jacobi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_double, _P, _P]),
+    "cta_jacobi_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(_CgOpts), ctypes.c_double,
+                                        ctypes.POINTER(_CgInfo), _P]),
+    "cta_op_set_multigrid": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_double]),
+    "cta_op_multigrid_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), _I64P,
+                                             ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
+    "cta_apply_multigrid": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "cta_prof_enable": (ctypes.c_int, [ctypes.c_int]),
     "cta_prof_reset": (ctypes.c_int, []),
     "cta_prof_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t,
@@ -332,6 +339,49 @@ def cta_tune_preconditioner(h, B, X, candidates, stream=None, **opts):
                                                   cs, len(candidates), ctypes.byref(best),
                                                   _stream(stream)))
     return best.value
+
+
+def cta_apply_jacobi(h, R, Z, omega=1.0, dot=None, stream=None):
+    """Z = omega R / diag(N) elementwise; <R, Z> to ``dot`` when given."""
+    dp = _dev(dot, "dot") if dot is not None else None
+    _check(load_library().cta_apply_jacobi(h, _dev(R, "R"), _dev(Z, "Z"), _dt(R), float(omega), dp,
+                                           _stream(stream)))
+    return Z
+
+
+def cta_jacobi_solve(h, B, X, omega, stream=None, **opts):
+    """Stationary damped Jacobi for N(X) = B (precision 'f64' or 'f32')."""
+    o = _opts(**opts)
+    info = _CgInfo()
+    st = load_library().cta_jacobi_solve(h, _dev(B, "B"), _dev(X, "X"), _dt(B), ctypes.byref(o), float(omega),
+                                         ctypes.byref(info), _stream(stream))
+    _check(st, allow_not_converged=True)
+    return _info_dict(info)
+
+
+def cta_op_set_multigrid(h, max_levels=8, coarse_max=2048, nu=1, omega_scale=1.5):
+    _check(load_library().cta_op_set_multigrid(h, int(max_levels), int(coarse_max), int(nu),
+                                               float(omega_scale)))
+
+
+def cta_op_multigrid_info(h, order):
+    """{"levels": L, "extents": [[n_k] per scale], "omega": [per scale]}."""
+    lib = load_library()
+    lv = ctypes.c_int(0)
+    _check(lib.cta_op_multigrid_info(h, ctypes.byref(lv), None, None, 0))
+    L = lv.value
+    ext = (ctypes.c_int64 * max(1, L * order))()
+    om = (ctypes.c_double * max(1, L))()
+    _check(lib.cta_op_multigrid_info(h, ctypes.byref(lv), ext, om, L))
+    return {"levels": L, "extents": [tuple(ext[l * order:(l + 1) * order]) for l in range(L)],
+            "omega": [om[l] for l in range(L)]}
+
+
+def cta_apply_multigrid(h, R, Z, chain="f32", dot=None, stream=None):
+    dp = _dev(dot, "dot") if dot is not None else None
+    _check(load_library().cta_apply_multigrid(h, _dev(R, "R"), _dev(Z, "Z"), _dt(R), _PREC[chain], dp,
+                                              _stream(stream)))
+    return Z
 
 
 def cta_tune_op(h, chain="bf16", reps=5, stream=None):
@@ -561,6 +611,31 @@ class Operator:
             X = torch.zeros_like(B)
         info = cta_cg_solve(self.handle, B, X, stream, **opts)
         return X, info
+
+    def jacobi(self, R, Z=None, omega=1.0, dot=None, stream=None):
+        torch = _torch()
+        if Z is None:
+            Z = torch.empty_like(R)
+        return cta_apply_jacobi(self.handle, R, Z, omega, dot, stream)
+
+    def jacobi_solve(self, B, omega, X=None, stream=None, **opts):
+        torch = _torch()
+        if X is None:
+            X = torch.zeros_like(B)
+        info = cta_jacobi_solve(self.handle, B, X, omega, stream, **opts)
+        return X, info
+
+    def set_multigrid(self, max_levels=8, coarse_max=2048, nu=1, omega_scale=1.5):
+        cta_op_set_multigrid(self.handle, max_levels, coarse_max, nu, omega_scale)
+
+    def multigrid_info(self):
+        return cta_op_multigrid_info(self.handle, len(self.n))
+
+    def multigrid(self, R, Z=None, chain="f32", dot=None, stream=None):
+        torch = _torch()
+        if Z is None:
+            Z = torch.empty_like(R)
+        return cta_apply_multigrid(self.handle, R, Z, chain, dot, stream)
 
 
 # ---------------------------------------------------------------- scattered operator

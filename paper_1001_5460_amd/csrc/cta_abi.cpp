@@ -150,13 +150,13 @@ static cta_status apply_normal_band(cta_op_s* op, const void* P, void* Q, int pr
 
 cta_status apply_normal(cta_op_s* op, const void* P, void* Q, int prec, int post,
                         double* dot_out, bool fuse_update, hipStream_t s, void* xsol,
-                        const void* fuse_src) {
-    if (op->use_band && !fuse_update && (prec == CTA_PREC_F64 || prec == CTA_PREC_F32) &&
+                        const void* fuse_src, const int* gate) {
+    if (op->use_band && !fuse_update && !gate && (prec == CTA_PREC_F64 || prec == CTA_PREC_F32) &&
         (post == POST_NONE || post == POST_DOT))
         return apply_normal_band(op, P, Q, prec, post, dot_out, s);
     const int N = op->order;
     const int tc = prec_tc(prec), tv = prec_tvec(prec);
-    const int* done = fuse_update ? &op->scal->done : nullptr;
+    const int* done = gate ? gate : (fuse_update ? &op->scal->done : nullptr);
     const int a = N - 2, b = N - 1;
     const int64_t nblk = op->N / (op->n[a] * op->n[b]);
     if (!tail_fits(tc, (int)op->n[a], (int)op->n[b]))
@@ -302,7 +302,7 @@ std::vector<int> plan_order(int N, const int64_t* in_ext, const int64_t* out_ext
 // the two work buffers (each >= max intermediate elements * size(tc)).
 cta_status run_chain(int N, const int64_t* in_ext, const int64_t* out_ext, const Mat* mats,
                      const std::vector<int>& order, const void* X, int tin, void* Y, int tout,
-                     int tc, void* w0, void* w1, hipStream_t s, const ChainBand* band) {
+                     int tc, void* w0, void* w1, hipStream_t s, const ChainBand* band, const int* gate) {
     int64_t cur[CTA_MAX_ORDER];
     int64_t tot = 1;
     for (int k = 0; k < N; ++k) {
@@ -335,9 +335,9 @@ cta_status run_chain(int N, const int64_t* in_ext, const int64_t* out_ext, const
         if (band && trail > 1)
             e = launch_rect_band(tc, src, dst, band->lo[k], band->coef[k], band->w, lead, K, J, trail, s);
         else if (trail == 1)
-            e = launch_contig(tc, src, dst, mats[k], lead, K, J, nullptr, s);
+            e = launch_contig(tc, src, dst, mats[k], lead, K, J, gate, s);
         else
-            e = launch_strided(tc, src, dst, mats[k], lead, K, J, trail, nullptr, s);
+            e = launch_strided(tc, src, dst, mats[k], lead, K, J, trail, gate, s);
         if (e != hipSuccess) return fail(CTA_ERR_HIP, "mode %d pass launch: %s", k, hipGetErrorString(e));
         tot = tot / cur[k] * J;
         cur[k] = J;
@@ -350,6 +350,174 @@ cta_status run_chain(int N, const int64_t* in_ext, const int64_t* out_ext, const
     return CTA_OK;
 }
 
+}  // namespace cta
+
+namespace cta {
+// Everything of a handle that follows from G_k, R_k (and, when Ah is given,
+// the collocation factors A_k): device copies, bands, work vectors, scalars.
+// op->order, n, m, lam, lift and user_order must be set; on failure the
+// caller destroys the handle.
+cta_status op_build(cta_op_s* op, std::vector<std::vector<double>>& G, std::vector<std::vector<double>>& R,
+                    const std::vector<bool>& has_reg, const std::vector<std::vector<double>>* Ah) {
+    std::vector<std::vector<double>> none;
+    const std::vector<std::vector<double>>& A = Ah ? *Ah : none;
+    op->has_A = Ah != nullptr;
+    op->N = 1;
+    op->Msamp = 1;
+    int64_t big = 1;
+    for (int k = 0; k < op->order; ++k) {
+        op->N *= op->n[k];
+        op->Msamp *= op->m[k];
+        big *= std::max(op->n[k], op->m[k]);
+    }
+    op->big = big;
+    for (int k = 0; k < op->order; ++k) {
+        op->hG[k] = G[k];
+        op->hR[k] = R[k];
+    }
+    cta_status st = CTA_OK;
+    auto& al = op->allocs;
+    size_t& acc = op->dev_bytes;
+    for (int k = 0; k < op->order && st == CTA_OK; ++k) {
+        const int nk = (int)op->n[k], mk = (int)op->m[k];
+        for (int dt = 0; dt < 3 && st == CTA_OK; ++dt)
+            st = upload_mat(G[k].data(), nk, nk, false, dt, &op->G[dt][k], al, acc);
+        for (int dt = 0; dt < 2 && st == CTA_OK && Ah; ++dt) {
+            st = upload_mat(A[k].data(), mk, nk, false, dt, &op->A[dt][k], al, acc);
+            if (st == CTA_OK) st = upload_mat(A[k].data(), mk, nk, true, dt, &op->At[dt][k], al, acc);
+        }
+        if (st == CTA_OK && has_reg[k]) {
+            std::vector<double> band64(nk * 5, 0.0);
+            std::vector<float> band32(nk * 5, 0.f);
+            for (int i = 0; i < nk; ++i)
+                for (int d = -2; d <= 2; ++d)
+                    if (i + d >= 0 && i + d < nk) {
+                        band64[i * 5 + d + 2] = R[k][(size_t)i * nk + i + d];
+                        band32[i * 5 + d + 2] = (float)R[k][(size_t)i * nk + i + d];
+                    }
+            st = dev_alloc(&op->rband[0][k], band64.size() * 8, al, acc);
+            if (st == CTA_OK) st = dev_alloc(&op->rband[1][k], band32.size() * 4, al, acc);
+            if (st == CTA_OK &&
+                (hipMemcpy(op->rband[0][k], band64.data(), band64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(op->rband[1][k], band32.data(), band32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+                st = fail(CTA_ERR_HIP, "copy of regulariser bands failed");
+        }
+    }
+    // banded Grams (B-spline collocation gives half-bandwidth 3): the band of
+    // every G_k when all are within half-bandwidth kBandMax
+    if (st == CTA_OK) {
+        constexpr int kBandMax = 4;
+        int w = 0;
+        for (int k = 0; k < op->order; ++k) {
+            const int nk = (int)op->n[k];
+            for (int i = 0; i < nk; ++i)
+                for (int j = 0; j < nk; ++j)
+                    if (G[k][(size_t)i * nk + j] != 0.0) w = std::max(w, std::abs(i - j));
+        }
+        op->band_w = w;
+        if (w <= kBandMax) {
+            const int wd = 2 * w + 1;
+            for (int k = 0; k < op->order && st == CTA_OK; ++k) {
+                const int nk = (int)op->n[k];
+                std::vector<double> b64((size_t)nk * wd, 0.0);
+                std::vector<float> b32((size_t)nk * wd, 0.f);
+                for (int i = 0; i < nk; ++i)
+                    for (int d = -w; d <= w; ++d)
+                        if (i + d >= 0 && i + d < nk) {
+                            b64[(size_t)i * wd + d + w] = G[k][(size_t)i * nk + i + d];
+                            b32[(size_t)i * wd + d + w] = (float)G[k][(size_t)i * nk + i + d];
+                        }
+                st = dev_alloc(&op->gband[0][k], b64.size() * 8, al, acc);
+                if (st == CTA_OK) st = dev_alloc(&op->gband[1][k], b32.size() * 4, al, acc);
+                if (st == CTA_OK &&
+                    (hipMemcpy(op->gband[0][k], b64.data(), b64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+                     hipMemcpy(op->gband[1][k], b32.data(), b32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+                    st = fail(CTA_ERR_HIP, "copy of the Gram bands failed");
+            }
+            op->band_ok = op->use_band = st == CTA_OK && op->N < ((int64_t)1 << 30);
+        }
+    }
+    // banded rows of A_k and A_k^T for the forward and right-hand-side chains:
+    // the span of each row's nonzeros, rounded up to 4, 6 or 8 columns
+    for (int dir = 0; dir < 2 && st == CTA_OK && op->band_ok && Ah; ++dir) {
+        int wmax = 0;
+        std::vector<std::vector<int>> los(op->order);
+        for (int k = 0; k < op->order; ++k) {
+            const int nk = (int)op->n[k], mk = (int)op->m[k];
+            const int rows = dir == 0 ? mk : nk, cols = dir == 0 ? nk : mk;
+            los[k].assign(rows, 0);
+            for (int r = 0; r < rows; ++r) {
+                int first = -1, last = -1;
+                for (int c = 0; c < cols; ++c) {
+                    const double v = dir == 0 ? A[k][(size_t)r * nk + c] : A[k][(size_t)c * nk + r];
+                    if (v != 0.0) {
+                        if (first < 0) first = c;
+                        last = c;
+                    }
+                }
+                los[k][r] = first < 0 ? 0 : first;
+                wmax = std::max(wmax, first < 0 ? 0 : last - first + 1);
+            }
+        }
+        if (wmax > 8) continue;
+        const int w = wmax <= 4 ? 4 : wmax <= 6 ? 6 : 8;
+        for (int k = 0; k < op->order && st == CTA_OK; ++k) {
+            const int nk = (int)op->n[k], mk = (int)op->m[k];
+            const int rows = dir == 0 ? mk : nk, cols = dir == 0 ? nk : mk;
+            std::vector<double> c64((size_t)rows * w, 0.0);
+            std::vector<float> c32((size_t)rows * w, 0.f);
+            for (int r = 0; r < rows; ++r)
+                for (int c = 0; c < w; ++c) {
+                    const int col = los[k][r] + c;
+                    if (col >= cols) continue;
+                    const double v = dir == 0 ? A[k][(size_t)r * nk + col] : A[k][(size_t)col * nk + r];
+                    c64[(size_t)r * w + c] = v;
+                    c32[(size_t)r * w + c] = (float)v;
+                }
+            st = dev_alloc((void**)&op->cb_lo[dir][k], (size_t)rows * 4, al, acc);
+            if (st == CTA_OK) st = dev_alloc(&op->cb_coef[dir][0][k], c64.size() * 8, al, acc);
+            if (st == CTA_OK) st = dev_alloc(&op->cb_coef[dir][1][k], c32.size() * 4, al, acc);
+            if (st == CTA_OK &&
+                (hipMemcpy(op->cb_lo[dir][k], los[k].data(), (size_t)rows * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(op->cb_coef[dir][0][k], c64.data(), c64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(op->cb_coef[dir][1][k], c32.data(), c32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+                st = fail(CTA_ERR_HIP, "copy of the factor bands failed");
+        }
+        if (st == CTA_OK) {
+            op->cb_ok[dir] = true;
+            op->cb_w[dir] = w;
+        }
+    }
+    const size_t vb = (size_t)op->N * 8;
+    void** vecs[] = {&op->T1, &op->T2, &op->vx, &op->vr, &op->vp, &op->vq, &op->vaux};
+    for (void** v : vecs)
+        if (st == CTA_OK) st = dev_alloc(v, vb, al, acc);
+    if (st == CTA_OK) st = dev_alloc((void**)&op->scal, sizeof(CgScalars), al, acc);
+    if (st == CTA_OK) st = dev_alloc((void**)&op->partials, kMaxGrid * sizeof(double), al, acc);
+    if (st == CTA_OK) st = dev_alloc((void**)&op->partials2, kMaxGrid * sizeof(double), al, acc);
+    // per-mode diagonals of G_k and R_k: the main diagonal of N is formed from
+    // them on the fly (Jacobi steps of Fig. Tensor_Jacobi)
+    for (int k = 0; k < op->order && st == CTA_OK; ++k) {
+        const int nk = (int)op->n[k];
+        std::vector<double> dg(nk), dr(nk);
+        for (int i = 0; i < nk; ++i) {
+            dg[i] = G[k][(size_t)i * nk + i];
+            dr[i] = has_reg[k] ? R[k][(size_t)i * nk + i] : 0.0;
+        }
+        st = dev_alloc((void**)&op->dgm[k], (size_t)nk * 8, al, acc);
+        if (st == CTA_OK && has_reg[k]) st = dev_alloc((void**)&op->drm[k], (size_t)nk * 8, al, acc);
+        if (st == CTA_OK && hipMemcpy(op->dgm[k], dg.data(), (size_t)nk * 8, hipMemcpyHostToDevice) != hipSuccess)
+            st = fail(CTA_ERR_HIP, "copy of the diagonal of G_k failed");
+        if (st == CTA_OK && has_reg[k] &&
+            hipMemcpy(op->drm[k], dr.data(), (size_t)nk * 8, hipMemcpyHostToDevice) != hipSuccess)
+            st = fail(CTA_ERR_HIP, "copy of the diagonal of R_k failed");
+    }
+    if (st == CTA_OK && hipMemset(op->scal, 0, sizeof(CgScalars)) != hipSuccess)
+        st = fail(CTA_ERR_HIP, "hipMemset of the scalars failed");
+    if (st == CTA_OK && hipHostMalloc((void**)&op->hscal, sizeof(CgScalars), hipHostMallocDefault) != hipSuccess)
+        st = fail(CTA_ERR_NOMEM, "hipHostMalloc of the scalar mirror failed");
+    return st;
+}
 }  // namespace cta
 
 // ---------------------------------------------------------------------------
@@ -422,142 +590,7 @@ extern "C" cta_status cta_op_create(cta_op* out, int order, const int64_t* n, co
             has_reg[k] = true;
         }
     }
-    op->N = 1;
-    op->Msamp = 1;
-    int64_t big = 1;
-    for (int k = 0; k < op->order; ++k) {
-        op->N *= op->n[k];
-        op->Msamp *= op->m[k];
-        big *= std::max(op->n[k], op->m[k]);
-    }
-    op->big = big;
-    for (int k = 0; k < op->order; ++k) {
-        op->hG[k] = G[k];
-        op->hR[k] = R[k];
-    }
-    cta_status st = CTA_OK;
-    auto& al = op->allocs;
-    size_t& acc = op->dev_bytes;
-    for (int k = 0; k < op->order && st == CTA_OK; ++k) {
-        const int nk = (int)op->n[k], mk = (int)op->m[k];
-        for (int dt = 0; dt < 3 && st == CTA_OK; ++dt)
-            st = upload_mat(G[k].data(), nk, nk, false, dt, &op->G[dt][k], al, acc);
-        for (int dt = 0; dt < 2 && st == CTA_OK; ++dt) {
-            st = upload_mat(A[k].data(), mk, nk, false, dt, &op->A[dt][k], al, acc);
-            if (st == CTA_OK) st = upload_mat(A[k].data(), mk, nk, true, dt, &op->At[dt][k], al, acc);
-        }
-        if (st == CTA_OK && has_reg[k]) {
-            std::vector<double> band64(nk * 5, 0.0);
-            std::vector<float> band32(nk * 5, 0.f);
-            for (int i = 0; i < nk; ++i)
-                for (int d = -2; d <= 2; ++d)
-                    if (i + d >= 0 && i + d < nk) {
-                        band64[i * 5 + d + 2] = R[k][(size_t)i * nk + i + d];
-                        band32[i * 5 + d + 2] = (float)R[k][(size_t)i * nk + i + d];
-                    }
-            st = dev_alloc(&op->rband[0][k], band64.size() * 8, al, acc);
-            if (st == CTA_OK) st = dev_alloc(&op->rband[1][k], band32.size() * 4, al, acc);
-            if (st == CTA_OK &&
-                (hipMemcpy(op->rband[0][k], band64.data(), band64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-                 hipMemcpy(op->rband[1][k], band32.data(), band32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
-                st = fail(CTA_ERR_HIP, "copy of regulariser bands failed");
-        }
-    }
-    // banded Grams (B-spline collocation gives half-bandwidth 3): the band of
-    // every G_k when all are within half-bandwidth kBandMax
-    if (st == CTA_OK) {
-        constexpr int kBandMax = 4;
-        int w = 0;
-        for (int k = 0; k < op->order; ++k) {
-            const int nk = (int)op->n[k];
-            for (int i = 0; i < nk; ++i)
-                for (int j = 0; j < nk; ++j)
-                    if (G[k][(size_t)i * nk + j] != 0.0) w = std::max(w, std::abs(i - j));
-        }
-        op->band_w = w;
-        if (w <= kBandMax) {
-            const int wd = 2 * w + 1;
-            for (int k = 0; k < op->order && st == CTA_OK; ++k) {
-                const int nk = (int)op->n[k];
-                std::vector<double> b64((size_t)nk * wd, 0.0);
-                std::vector<float> b32((size_t)nk * wd, 0.f);
-                for (int i = 0; i < nk; ++i)
-                    for (int d = -w; d <= w; ++d)
-                        if (i + d >= 0 && i + d < nk) {
-                            b64[(size_t)i * wd + d + w] = G[k][(size_t)i * nk + i + d];
-                            b32[(size_t)i * wd + d + w] = (float)G[k][(size_t)i * nk + i + d];
-                        }
-                st = dev_alloc(&op->gband[0][k], b64.size() * 8, al, acc);
-                if (st == CTA_OK) st = dev_alloc(&op->gband[1][k], b32.size() * 4, al, acc);
-                if (st == CTA_OK &&
-                    (hipMemcpy(op->gband[0][k], b64.data(), b64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-                     hipMemcpy(op->gband[1][k], b32.data(), b32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
-                    st = fail(CTA_ERR_HIP, "copy of the Gram bands failed");
-            }
-            op->band_ok = op->use_band = st == CTA_OK && op->N < ((int64_t)1 << 30);
-        }
-    }
-    // banded rows of A_k and A_k^T for the forward and right-hand-side chains:
-    // the span of each row's nonzeros, rounded up to 4, 6 or 8 columns
-    for (int dir = 0; dir < 2 && st == CTA_OK && op->band_ok; ++dir) {
-        int wmax = 0;
-        std::vector<std::vector<int>> los(op->order);
-        for (int k = 0; k < op->order; ++k) {
-            const int nk = (int)op->n[k], mk = (int)op->m[k];
-            const int rows = dir == 0 ? mk : nk, cols = dir == 0 ? nk : mk;
-            los[k].assign(rows, 0);
-            for (int r = 0; r < rows; ++r) {
-                int first = -1, last = -1;
-                for (int c = 0; c < cols; ++c) {
-                    const double v = dir == 0 ? A[k][(size_t)r * nk + c] : A[k][(size_t)c * nk + r];
-                    if (v != 0.0) {
-                        if (first < 0) first = c;
-                        last = c;
-                    }
-                }
-                los[k][r] = first < 0 ? 0 : first;
-                wmax = std::max(wmax, first < 0 ? 0 : last - first + 1);
-            }
-        }
-        if (wmax > 8) continue;
-        const int w = wmax <= 4 ? 4 : wmax <= 6 ? 6 : 8;
-        for (int k = 0; k < op->order && st == CTA_OK; ++k) {
-            const int nk = (int)op->n[k], mk = (int)op->m[k];
-            const int rows = dir == 0 ? mk : nk, cols = dir == 0 ? nk : mk;
-            std::vector<double> c64((size_t)rows * w, 0.0);
-            std::vector<float> c32((size_t)rows * w, 0.f);
-            for (int r = 0; r < rows; ++r)
-                for (int c = 0; c < w; ++c) {
-                    const int col = los[k][r] + c;
-                    if (col >= cols) continue;
-                    const double v = dir == 0 ? A[k][(size_t)r * nk + col] : A[k][(size_t)col * nk + r];
-                    c64[(size_t)r * w + c] = v;
-                    c32[(size_t)r * w + c] = (float)v;
-                }
-            st = dev_alloc((void**)&op->cb_lo[dir][k], (size_t)rows * 4, al, acc);
-            if (st == CTA_OK) st = dev_alloc(&op->cb_coef[dir][0][k], c64.size() * 8, al, acc);
-            if (st == CTA_OK) st = dev_alloc(&op->cb_coef[dir][1][k], c32.size() * 4, al, acc);
-            if (st == CTA_OK &&
-                (hipMemcpy(op->cb_lo[dir][k], los[k].data(), (size_t)rows * 4, hipMemcpyHostToDevice) != hipSuccess ||
-                 hipMemcpy(op->cb_coef[dir][0][k], c64.data(), c64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-                 hipMemcpy(op->cb_coef[dir][1][k], c32.data(), c32.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
-                st = fail(CTA_ERR_HIP, "copy of the factor bands failed");
-        }
-        if (st == CTA_OK) {
-            op->cb_ok[dir] = true;
-            op->cb_w[dir] = w;
-        }
-    }
-    const size_t vb = (size_t)op->N * 8;
-    void** vecs[] = {&op->T1, &op->T2, &op->vx, &op->vr, &op->vp, &op->vq, &op->vaux};
-    for (void** v : vecs)
-        if (st == CTA_OK) st = dev_alloc(v, vb, al, acc);
-    if (st == CTA_OK) st = dev_alloc((void**)&op->scal, sizeof(CgScalars), al, acc);
-    if (st == CTA_OK) st = dev_alloc((void**)&op->partials, kMaxGrid * sizeof(double), al, acc);
-    if (st == CTA_OK && hipMemset(op->scal, 0, sizeof(CgScalars)) != hipSuccess)
-        st = fail(CTA_ERR_HIP, "hipMemset of the scalars failed");
-    if (st == CTA_OK && hipHostMalloc((void**)&op->hscal, sizeof(CgScalars), hipHostMallocDefault) != hipSuccess)
-        st = fail(CTA_ERR_NOMEM, "hipHostMalloc of the scalar mirror failed");
+    cta_status st = cta::op_build(op, G, R, has_reg, &A);
     if (st != CTA_OK) {
         std::string keep = g_err;
         cta_op_destroy(op);
@@ -571,6 +604,7 @@ extern "C" cta_status cta_op_create(cta_op* out, int order, const int64_t* n, co
 extern "C" cta_status cta_op_destroy(cta_op op) {
     if (!op) return CTA_OK;
     (void)hipDeviceSynchronize();
+    cta::mg_release(op);
     for (void* p : op->allocs) (void)hipFree(p);
     if (op->hscal) (void)hipHostFree(op->hscal);
     delete op;
@@ -601,6 +635,7 @@ static cta_status op_chain(cta_op op, const void* X, cta_dtype xd, void* Y, cta_
     if (st != CTA_OK) return st;
     if (chain != CTA_PREC_F64 && chain != CTA_PREC_F32)
         return fail(CTA_ERR_ARG, "forward/rhs chains run in CTA_PREC_F64 or CTA_PREC_F32");
+    if (!op->has_A) return fail(CTA_ERR_ARG, "this handle has no collocation factors");
     st = ensure_chain_ws(op);
     if (st != CTA_OK) return st;
     const int tc = prec_tc(chain);
@@ -687,12 +722,12 @@ static cta_status read_scal(cta_op_s* op, hipStream_t s) {
 // Inner CG loop on the handle's vectors: x (vx or the user's X), r = vr, p = vp,
 // q = vq, with scal->rho and scal->bnorm2 already set.  Returns the final done flag.
 cta_status cg_loop(cta_op_s* op, void* x, int prec, double rtol, int max_iter, int check_every,
-                   hipStream_t s, int* done_out, int* iters_out, bool pc) {
+                   hipStream_t s, int* done_out, int* iters_out, int pc) {
     const int tv = prec_tvec(prec);
     const size_t vb = (size_t)op->N * dt_size(tv);
     CTA_HIP(launch_fill_zero(op->vp, vb, s));
     // preconditioned: z = M^-1 r in vaux and <r, z> before the first step
-    if (pc) CTA_TRY(apply_precond(op, op->vr, op->vaux, prec, POST_DOT, &op->scal->rz, false, s));
+    if (pc) CTA_TRY(precond_apply(op, pc, op->vr, op->vaux, prec, POST_DOT, &op->scal->rz, false, s));
     CTA_HIP(launch_cg_setup(op->scal, rtol * rtol, max_iter, s, pc ? 1 : 0));
     if (check_every < 1) check_every = 1;
     // x += alpha p of each step is applied by the next step's tail pass (which
@@ -701,13 +736,10 @@ cta_status cg_loop(cta_op_s* op, void* x, int prec, double rtol, int max_iter, i
         for (int c = 0; c < check_every; ++c) {
             CTA_TRY(apply_normal(op, nullptr, op->vq, prec, POST_ALPHA, nullptr, true, s, x,
                                  pc ? op->vaux : nullptr));
-            if (pc && prec == CTA_PREC_BF16) {
-                // r -= alpha q fused into the preconditioner's first pass
-                CTA_TRY(apply_precond(op, op->vr, op->vaux, prec, POST_RZ, nullptr, true, s, true));
-            } else {
+            if (pc)
+                CTA_TRY(precond_step(op, pc, prec, s));
+            else
                 CTA_HIP(launch_cg_update(tv, nullptr, op->vr, op->vp, op->vq, op->N, op->partials, op->scal, s));
-                if (pc) CTA_TRY(apply_precond(op, op->vr, op->vaux, prec, POST_RZ, nullptr, true, s));
-            }
         }
         CTA_TRY(read_scal(op, s));
         if (op->hscal->done != DONE_RUNNING) break;
@@ -755,8 +787,11 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
     const int prec = opts->precision;
     if (prec < CTA_PREC_F64 || prec > CTA_PREC_BF16_RELIABLE) return fail(CTA_ERR_ARG, "bad precision");
     const bool mixed = prec == CTA_PREC_BF16_REFINE || prec == CTA_PREC_BF16_RELIABLE;
-    const bool pc = opts->precond != 0;
-    if (pc && !op->has_pc) return fail(CTA_ERR_ARG, "precond = 1 but no preconditioner was set");
+    const int pc = opts->precond;
+    if (pc < PC_NONE || pc > PC_MULTIGRID) return fail(CTA_ERR_ARG, "precond must be 0, 1, 2 or 3");
+    if (pc == PC_TENSOR_INV && !op->has_pc) return fail(CTA_ERR_ARG, "precond = 1 but no preconditioner was set");
+    if (pc == PC_MULTIGRID && op->mg.empty())
+        return fail(CTA_ERR_ARG, "precond = 3 but no multigrid hierarchy was set (cta_op_set_multigrid)");
     if (!(opts->rtol >= 0) || opts->max_iter < 0) return fail(CTA_ERR_ARG, "bad rtol or max_iter");
     const int want = (prec == CTA_PREC_F64 || mixed) ? DT_F64 : DT_F32;
     if ((int)dtype != want)
@@ -871,7 +906,8 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
                 // update (or a little below the target, which the true residual then checks)
                 const double thr = std::max(eta * eta * rr, 0.25 * target);
                 if (pc)
-                    CTA_TRY(apply_precond(op, op->vr, op->vaux, CTA_PREC_BF16, POST_DOT, &op->scal->dot2, false, s));
+                    CTA_TRY(precond_apply(op, pc, op->vr, op->vaux, CTA_PREC_BF16, POST_DOT, &op->scal->dot2, false,
+                                          s));
                 CTA_HIP(launch_cg_group(op->scal, thr, opts->max_iter, steps > 0 ? 1 : 0, s, pc ? 1 : 0));
                 int gdone = DONE_RUNNING;
                 for (int chunk = first_chunk;; chunk = later_chunk) {
@@ -879,9 +915,7 @@ extern "C" cta_status cta_cg_solve(cta_op op, const void* B, void* X, cta_dtype 
                         CTA_TRY(apply_normal(op, nullptr, op->vq, CTA_PREC_BF16, POST_ALPHA, nullptr, true, s,
                                              op->vx, pc ? op->vaux : nullptr));
                         if (pc) {
-                            // r -= alpha q fused into the preconditioner's first pass
-                            CTA_TRY(apply_precond(op, op->vr, op->vaux, CTA_PREC_BF16, POST_RZ, nullptr, true, s,
-                                                  true));
+                            CTA_TRY(precond_step(op, pc, CTA_PREC_BF16, s));
                         } else {
                             CTA_HIP(launch_cg_update(DT_F32, nullptr, op->vr, op->vp, op->vq, n, op->partials,
                                                      op->scal, s));
@@ -1120,7 +1154,7 @@ extern "C" int cta_op_band_width(cta_op op) { return op ? op->band_w : -1; }
 // ---------------------------------------------------------------------------
 // Tensor-inverse preconditioner: (G_k + c R_k)^-1 per mode, by Cholesky
 // factorisation and forward / back substitution of the unit vectors (FP64).
-namespace {
+namespace cta {
 bool spd_inverse(const std::vector<double>& A, int n, std::vector<double>& inv) {
     std::vector<double> L((size_t)n * n, 0.0);
     for (int j = 0; j < n; ++j) {
@@ -1151,7 +1185,9 @@ bool spd_inverse(const std::vector<double>& A, int n, std::vector<double>& inv) 
     }
     return true;
 }
+}  // namespace cta
 
+namespace {
 void release_mat(cta_op_s* op, Mat& m) {
     if (!m.p) return;
     void* p = const_cast<void*>(m.p);

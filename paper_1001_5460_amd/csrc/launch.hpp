@@ -166,6 +166,42 @@ hipError_t launch_fill_pattern(int tv, void* x, int64_t n, hipStream_t s);
 // X64 += (double) d32
 hipError_t launch_add_f64(double* X, const void* d, int td, int64_t n, hipStream_t s);
 
+// ---------------------------------------------------------------- diagonal and multigrid
+// Main diagonal of the normal operator from per-mode diagonals:
+// d[i] = prod_k g[k][i_k] + lam * sum_k r[k][i_k] (r[k] may be NULL); fmul/fsh
+// are the multiply-high division constants of ext[k] (fastdiv_init).  Flat
+// indices must stay below 2^31.
+struct DiagDesc {
+    const double* g[8];
+    const double* r[8];
+    int ext[8];
+    uint32_t fmul[8];
+    int fsh[8];
+    int order;
+    double lam;
+};
+// z = omega r / d; with post != POST_NONE also <r, z> (finalized with `post`).
+// Skipped entirely when *gate is set (gate may be NULL).
+hipError_t launch_jacobi_apply(int tv, const void* r, void* z, int64_t n, const DiagDesc& d, double omega,
+                               double* partials, CgScalars* scal, int post, double* out, const int* gate,
+                               hipStream_t s);
+// Preconditioned CG step with the diagonal: r -= alpha q, z = r / d; <r, r>
+// finalized with POST_RHO (stopping test) and <r, z> with POST_RZ (beta).
+hipError_t launch_jacobi_update(int tv, void* r, const void* q, void* z, int64_t n, const DiagDesc& d,
+                                double* partials, double* partials2, CgScalars* scal, hipStream_t s);
+// Cout = C + omega (B - Q) / d with Q = N(C) (Cout may be C); dotmode 1:
+// ||B - Q||^2, 2: <B, C_new> (finalized with `post`), 0: no reduction.
+// Gated like launch_jacobi_apply.
+hipError_t launch_jacobi_correct(int tv, const void* C, void* Cout, const void* B, const void* Q, int64_t n,
+                                 const DiagDesc& d, double omega, int dotmode, double* partials,
+                                 CgScalars* scal, int post, double* out, const int* gate, hipStream_t s);
+// t = b - t and c += t (gated)
+hipError_t launch_mg_sub(int tv, void* t, const void* b, int64_t n, const int* gate, hipStream_t s);
+hipError_t launch_mg_add(int tv, void* c, const void* t, int64_t n, const int* gate, hipStream_t s);
+// y = M x for a row-major n x n matrix (gated)
+hipError_t launch_dense_matvec(int tv, const void* M, const void* x, void* y, int n, const int* gate,
+                               hipStream_t s);
+
 // ---------------------------------------------------------------- scattered operator
 // Brick geometry of the scattered-measurement operator (order N <= 4).  A
 // cell is one knot span per mode (C_k = n_k - 3 spans); a brick holds bc_k
