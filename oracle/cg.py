@@ -26,6 +26,14 @@ Readings where the figure is silent or garbled:
 * When the loop ends on the threshold, the residual is recomputed from the
   iterate; if that true residual misses the tolerance, the iteration starts
   over once from the current iterate.
+
+Storage model (the paper does not fix the precision): with ``store`` given
+(e.g. numpy.float32) the iterate, residual, direction and the operator's image
+are rounded to that type each time they are formed, while every inner product
+and scalar stays FP64.  This is the arithmetic of a solver that keeps its
+vectors in FP32 and reduces in FP64; it lets iteration counts of such a solver
+be compared with the same recurrence under the same rounding.  The default
+(no ``store``) is plain FP64.
 """
 from dataclasses import dataclass, field
 from typing import Callable, List, Optional
@@ -59,11 +67,12 @@ class _Log:
     res2: List[float] = field(default_factory=list)       # squared residual norms
 
 
-def _sweep(apply, rhs, x, tol2, budget, log):
-    """CG from iterate x for at most `budget` steps.
+def _sweep(apply, rhs, x, tol2, budget, log, keep):
+    """CG from iterate x for at most `budget` steps; `keep` rounds a vector to
+    the storage type.
 
     Returns (x, steps taken, status, last squared residual norm)."""
-    res = rhs - apply(x)
+    res = keep(rhs - apply(x))
     res2 = inner(res, res)
     log.res2.append(res2)
     if res2 <= tol2:
@@ -71,16 +80,16 @@ def _sweep(apply, rhs, x, tol2, budget, log):
     direction = res.copy()
     taken = 0
     while taken < budget:
-        image = apply(direction)
+        image = keep(apply(direction))
         curvature = inner(direction, image)
         if not np.isfinite(curvature) or curvature <= 0.0:
             return x, taken, BREAKDOWN, res2
         step = res2 / curvature
-        x = x + step * direction
-        res = res - step * image
+        x = keep(x + step * direction)
+        res = keep(res - step * image)
         res2_next = inner(res, res)
         ratio = res2_next / res2
-        direction = res + ratio * direction
+        direction = keep(res + ratio * direction)
         res2 = res2_next
         taken += 1
         log.steps.append(step)
@@ -99,20 +108,25 @@ def _true_relative_residual(apply, rhs, x, scale):
 
 
 def cg(apply: Callable, B, x0: Optional[np.ndarray] = None, rtol=1e-8,
-       max_iter=10000, restart=True) -> CGResult:
-    """Solve apply(X) = B by tensor CG (Fig. Tensor_CG) in float64."""
-    rhs = np.asarray(B, dtype=np.float64)
-    x = np.zeros_like(rhs) if x0 is None else np.array(x0, dtype=np.float64)
+       max_iter=10000, restart=True, store=None) -> CGResult:
+    """Solve apply(X) = B by tensor CG (Fig. Tensor_CG) in float64 (vectors
+    rounded to `store` when given, see the storage model above)."""
+    if store is None:
+        keep = lambda v: v  # noqa: E731
+    else:
+        keep = lambda v: np.asarray(v).astype(store).astype(np.float64)  # noqa: E731
+    rhs = keep(np.asarray(B, dtype=np.float64))
+    x = np.zeros_like(rhs) if x0 is None else keep(np.array(x0, dtype=np.float64))
     bnorm = np.sqrt(inner(rhs, rhs))
     scale = bnorm if bnorm > 0 else 1.0
     tol2 = (rtol * bnorm) ** 2
     log = _Log()
-    x, taken, status, res2 = _sweep(apply, rhs, x, tol2, max_iter, log)
+    x, taken, status, res2 = _sweep(apply, rhs, x, tol2, max_iter, log, keep)
     restarts = 0
     true_rel = _true_relative_residual(apply, rhs, x, scale)
     if restart and status == CONVERGED and true_rel > rtol and taken < max_iter:
         restarts = 1
-        x, more, status, res2 = _sweep(apply, rhs, x, tol2, max_iter - taken, log)
+        x, more, status, res2 = _sweep(apply, rhs, x, tol2, max_iter - taken, log, keep)
         taken += more
         true_rel = _true_relative_residual(apply, rhs, x, scale)
     if status == CONVERGED and true_rel > rtol:

@@ -150,3 +150,15 @@ def test_relative_residual_against_kronecker_matrix(n, lam):
     assert oracle.relative_residual(Xs, B, op) <= 1e-12
     assert oracle.relative_residual(X, np.zeros(n), op) == pytest.approx(
         np.linalg.norm(M @ X.reshape(-1)), rel=1e-12)
+
+
+def test_fp32_storage_model():
+    """store=float32 keeps every vector on the float32 grid and reaches the
+    tolerance that FP32 vectors allow; without it the oracle is unchanged."""
+    p, op, B = _problem((6, 5, 4), 1e-3)
+    a = oracle.cg(op, B, rtol=1e-10)
+    b = oracle.cg(op, B, rtol=1e-10, store=None)
+    assert np.array_equal(a.x, b.x) and a.iters == b.iters
+    c = oracle.cg(op, B, rtol=1e-5, store=np.float32)
+    assert np.array_equal(c.x, c.x.astype(np.float32).astype(np.float64))
+    assert c.status == CONVERGED and oracle.relative_residual(c.x, B, op) <= 1e-5
