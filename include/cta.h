@@ -174,7 +174,9 @@ cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
  * blocks of 32 with the whole stencil staged on chip, F32/BF16 chains of
  * order 3 or 4, else as 2; 5: persistent workgroups that load the next
  * tile while computing the current one, BF16 chains with 96 < n_1 <= 128,
- * else as 2). */
+ * else as 2; 6: as 5 with each thread owning 4 columns of 4 rows in the
+ * epilogue, so mode indices, band rows and gather offsets are formed once
+ * per tile). */
 cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3);
 cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3);
 
@@ -471,13 +473,18 @@ cta_status cta_sop_forward(cta_sop op, const void* X, void* y, cta_dtype dtype, 
 cta_status cta_sop_adjoint(cta_sop op, const void* y, void* B, cta_dtype dtype, void* stream);
 cta_status cta_sop_apply_normal(cta_sop op, const void* P, void* Q, cta_dtype dtype, double* dot,
                                 void* stream);
-/* Tensor CG (Fig. Tensor_CG) on the scattered normal operator from X = 0 in
- * the dtype's precision, stopping when ||r|| <= rtol ||B|| (recursive
- * residual), at most max_iter iterations; the host reads the flag every
- * check_every iterations.  Fills *host_info (rel_res_true recomputed in the
- * dtype's precision).  Returns CTA_OK, CTA_NOT_CONVERGED or an error. */
-cta_status cta_sop_cg_solve(cta_sop op, const void* B, void* X, cta_dtype dtype, double rtol,
-                            int max_iter, int check_every, cta_cg_info* host_info, void* stream);
+/* Tensor CG (Fig. Tensor_CG) on the scattered normal operator in the dtype's
+ * precision (F64 or F32 vectors, FP64 dots).  opts: rtol, max_iter,
+ * x0_given (X holds the start), fallback_zero (a start whose residual is
+ * not below ||B|| is replaced by zero), check_every (the host reads the flag
+ * every this many iterations); precision is taken from dtype and precond
+ * must be 0.  Stops when ||r|| <= rtol ||B|| (recursive residual); the true
+ * residual is then recomputed in the dtype's precision, and when it misses
+ * rtol the iteration restarts once from it.  Fills *host_info; returns
+ * CTA_OK only when the true residual meets rtol, else CTA_NOT_CONVERGED
+ * (the last X written) or an error.  Synchronises `stream`. */
+cta_status cta_sop_cg_solve(cta_sop op, const void* B, void* X, cta_dtype dtype, const cta_cg_opts* opts,
+                            cta_cg_info* host_info, void* stream);
 
 /* ------------------------------------------------------------------------
  * Kernel timing tracer.  When enabled, every kernel the library launches is
@@ -489,7 +496,8 @@ cta_status cta_sop_cg_solve(cta_sop op, const void* B, void* X, cta_dtype dtype,
  * full length is returned in *needed).  The active figures cover the
  * launches that ran at least a tenth of the kernel's 90th-percentile
  * duration: the iterations a solver enqueues past convergence exit at once on
- * the device-side converged flag, and they are left out there.  cta_prof_reset drops the records.  Process-wide; not meant for
+ * the device-side converged flag, and they are left out there.  cta_prof_reset drops the records (called
+ * with the tracer off it also destroys the tracer's HIP events).  Process-wide; not meant for
  * concurrent use from several threads.
  * ---------------------------------------------------------------------- */
 cta_status cta_prof_enable(int on);

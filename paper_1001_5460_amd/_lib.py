@@ -108,8 +108,8 @@ _SIGS = {
     "cta_sop_forward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     "cta_sop_adjoint": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     "cta_sop_apply_normal": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P]),
-    "cta_sop_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                        ctypes.c_int, ctypes.POINTER(_CgInfo), _P]),
+    "cta_sop_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(_CgOpts),
+                                        ctypes.POINTER(_CgInfo), _P]),
     "cta_apply_jacobi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_double, _P, _P]),
     "cta_jacobi_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(_CgOpts), ctypes.c_double,
                                         ctypes.POINTER(_CgInfo), _P]),
@@ -694,11 +694,12 @@ def cta_sop_apply_normal(h, P, Q, dot=None, stream=None):
     return Q
 
 
-def cta_sop_cg_solve(h, B, X, rtol=1e-6, max_iter=10000, check_every=16, stream=None):
+def cta_sop_cg_solve(h, B, X, rtol=1e-6, max_iter=10000, check_every=16, stream=None, **opts):
+    """CG on the scattered operator; options as in cta_cg_opts (x0_given, fallback_zero)."""
+    o = _opts(rtol=float(rtol), max_iter=int(max_iter), check_every=int(check_every), **opts)
     info = _CgInfo()
-    st = load_library().cta_sop_cg_solve(h, _dev(B, "B"), _dev(X, "X"), _dt(B), float(rtol),
-                                         int(max_iter), int(check_every), ctypes.byref(info),
-                                         _stream(stream))
+    st = load_library().cta_sop_cg_solve(h, _dev(B, "B"), _dev(X, "X"), _dt(B), ctypes.byref(o),
+                                         ctypes.byref(info), _stream(stream))
     _check(st, allow_not_converged=True)
     return _info_dict(info)
 
@@ -751,9 +752,9 @@ class ScatteredOperator:
             Q = torch.empty_like(P)
         return cta_sop_apply_normal(self.handle, P, Q, dot, stream)
 
-    def solve(self, B, X=None, rtol=1e-6, max_iter=10000, check_every=16, stream=None):
+    def solve(self, B, X=None, rtol=1e-6, max_iter=10000, check_every=16, stream=None, **opts):
         torch = _torch()
         if X is None:
             X = torch.empty_like(B)
-        info = cta_sop_cg_solve(self.handle, B, X, rtol, max_iter, check_every, stream)
+        info = cta_sop_cg_solve(self.handle, B, X, rtol, max_iter, check_every, stream, **opts)
         return X, info

@@ -91,6 +91,10 @@ struct cta_op_s {
     int mg_nu = 1;
     int mg_ncoarse = 0;               // unknowns of the coarsest scale
     void* mg_inv[2] = {nullptr, nullptr};  // its inverse matrix (F64, F32), row-major
+    // device copy of the batched solver's schedule when this handle is the
+    // first problem of a batch (reused by later calls, freed with the handle)
+    void* batch_buf = nullptr;
+    size_t batch_bytes = 0;
 };
 
 namespace cta {

@@ -434,28 +434,38 @@ static cta_status run_batched(int count, const cta_op* ops, const void* const* B
         plist.insert(plist.end(), lists[t].begin(), lists[t].end());
         ranges[t].y = (int)plist.size();
     }
-    // device copies (allocated per call; freed before returning)
-    std::vector<void*> allocs;
-    auto dalloc = [&](size_t bytes) -> void* {
-        void* p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
-        allocs.push_back(p);
-        return p;
-    };
-    auto cleanup = [&]() {
-        for (void* p : allocs) (void)hipFree(p);
-    };
-    BatchProblem* d_pb = (BatchProblem*)dalloc(sizeof(BatchProblem) * count);
-    int* d_plist = (int*)dalloc(sizeof(int) * count);
-    int2* d_rg = (int2*)dalloc(sizeof(int2) * T);
-    BatchResult* d_res = (BatchResult*)dalloc(sizeof(BatchResult) * count);
-    TeamSync* d_sync = (TeamSync*)dalloc(sizeof(TeamSync) * T);
-    double* d_part = (double*)dalloc(sizeof(double) * T * S * 4);
-    int* d_err = (int*)dalloc(sizeof(int) * 64);
-    if (!d_pb || !d_plist || !d_rg || !d_res || !d_sync || !d_part || !d_err) {
-        cleanup();
-        return fail(CTA_ERR_NOMEM, "allocation of the batched schedule failed");
+    // device copies of the schedule in one buffer owned by the first problem's
+    // handle: allocated on first use, grown when a larger set needs more, freed
+    // with that handle (a call synchronises its stream before returning, so
+    // the buffer is idle between calls)
+    auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) / 256 * 256; };
+    const size_t o_pb = 0;
+    const size_t o_pl = o_pb + al(sizeof(BatchProblem) * count);
+    const size_t o_rg = o_pl + al(sizeof(int) * count);
+    const size_t o_res = o_rg + al(sizeof(int2) * T);
+    const size_t o_sync = o_res + al(sizeof(BatchResult) * count);
+    const size_t o_part = o_sync + al(sizeof(TeamSync) * T);
+    const size_t o_err = o_part + al(sizeof(double) * T * S * 4);
+    const size_t total = o_err + al(sizeof(int) * 64);
+    cta_op_s* owner = ops[0];
+    if (owner->batch_bytes < total) {
+        if (owner->batch_buf) (void)hipFree(owner->batch_buf);
+        owner->batch_buf = nullptr;
+        owner->batch_bytes = 0;
+        if (hipMalloc(&owner->batch_buf, total) != hipSuccess) {
+            owner->batch_buf = nullptr;
+            return fail(CTA_ERR_NOMEM, "allocation of the batched schedule failed");
+        }
+        owner->batch_bytes = total;
     }
+    char* base = (char*)owner->batch_buf;
+    BatchProblem* d_pb = (BatchProblem*)(base + o_pb);
+    int* d_plist = (int*)(base + o_pl);
+    int2* d_rg = (int2*)(base + o_rg);
+    BatchResult* d_res = (BatchResult*)(base + o_res);
+    TeamSync* d_sync = (TeamSync*)(base + o_sync);
+    double* d_part = (double*)(base + o_part);
+    int* d_err = (int*)(base + o_err);
     hipError_t e = hipMemcpyAsync(d_pb, pbs.data(), sizeof(BatchProblem) * count, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_plist, plist.data(), sizeof(int) * count, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_rg, ranges.data(), sizeof(int2) * T, hipMemcpyHostToDevice, s);
@@ -491,7 +501,6 @@ static cta_status run_batched(int count, const cta_op* ops, const void* const* B
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    cleanup();
     if (e != hipSuccess) return fail(CTA_ERR_HIP, "batched launch: %s", hipGetErrorString(e));
     if (herr) return fail(CTA_ERR_HIP, "a team barrier exceeded its spin limit");
     if (kernel_ms) *kernel_ms = ms;

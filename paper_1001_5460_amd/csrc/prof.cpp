@@ -64,6 +64,10 @@ extern "C" cta_status cta_prof_enable(int on) {
     return CTA_OK;
 }
 
+// While the tracer is on, the events of dropped records go back to a pool for
+// the next launches; a reset with the tracer off destroys every event, so the
+// library holds no HIP events once tracing is done (none are left for the
+// runtime's own teardown at process exit).
 extern "C" cta_status cta_prof_reset(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (Rec& r : g_recs) {
@@ -72,6 +76,10 @@ extern "C" cta_status cta_prof_reset(void) {
         g_pool.push_back(r.b);
     }
     g_recs.clear();
+    if (!g_on) {
+        for (hipEvent_t e : g_pool) (void)hipEventDestroy(e);
+        g_pool.clear();
+    }
     return CTA_OK;
 }
 

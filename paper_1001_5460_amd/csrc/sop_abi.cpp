@@ -331,13 +331,16 @@ extern "C" cta_status cta_sop_apply_normal(cta_sop op, const void* P, void* Q, c
     return sop_normal(op, di, P, Q, dot ? POST_DOT : POST_NONE, dot, false, (hipStream_t)stream);
 }
 
-extern "C" cta_status cta_sop_cg_solve(cta_sop op, const void* B, void* X, cta_dtype dtype, double rtol,
-                                       int max_iter, int check_every, cta_cg_info* info, void* stream) {
-    if (!op || !B || !X || !info) return fail(CTA_ERR_ARG, "NULL argument");
+extern "C" cta_status cta_sop_cg_solve(cta_sop op, const void* B, void* X, cta_dtype dtype,
+                                       const cta_cg_opts* opts, cta_cg_info* info, void* stream) {
+    if (!op || !B || !X || !opts || !info) return fail(CTA_ERR_ARG, "NULL argument");
     if (B == X) return fail(CTA_ERR_ARG, "B and X must not overlap");
+    const double rtol = opts->rtol;
+    const int max_iter = opts->max_iter;
     if (!(rtol >= 0) || max_iter < 0) return fail(CTA_ERR_ARG, "bad rtol or max_iter");
     const int di = dtype_index(dtype);
     if (di < 0) return fail(CTA_ERR_DTYPE, "scattered operator: dtype must be CTA_F64 or CTA_F32");
+    if (opts->precond) return fail(CTA_ERR_UNSUPPORTED, "the scattered solver has no preconditioner");
     std::memset(info, 0, sizeof *info);
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
@@ -346,41 +349,77 @@ extern "C" cta_status cta_sop_cg_solve(cta_sop op, const void* B, void* X, cta_d
     const size_t vb = (size_t)n * (di == 0 ? 8 : 4);
     SOP_TRY(ensure_vectors(op, di));
     void *r = op->vec[di][0], *p = op->vec[di][1], *q = op->vec[di][2];
-    if (check_every < 1) check_every = 16;
-    // X = 0, r = B, rho = <B, B>
+    const int check_every = opts->check_every >= 1 ? opts->check_every : 16;
     SOP_HIP(launch_dot(dt, B, B, n, op->partials, op->scal, &op->scal->bnorm2, s));
-    SOP_HIP(launch_fill_zero(X, vb, s));
-    SOP_HIP(launch_cast(dt, dt, B, r, n, s));
-    SOP_HIP(launch_dot(dt, r, r, n, op->partials, op->scal, &op->scal->rho, s));
-    SOP_HIP(launch_fill_zero(p, vb, s));
-    SOP_HIP(launch_cg_setup(op->scal, rtol * rtol, max_iter, s, 0));
+    // starting residual: r = B - N(X) for a given start (replaced by zero with
+    // fallback_zero when it is not smaller than ||B||), else X = 0 and r = B
+    bool zero_start = !opts->x0_given;
+    if (opts->x0_given) {
+        SOP_TRY(sop_normal(op, di, X, q, POST_NONE, nullptr, false, s));
+        SOP_HIP(launch_residual(dt, dt, B, q, r, n, op->partials, op->scal, &op->scal->rho, s));
+        if (opts->fallback_zero) {
+            SOP_TRY(read_scal(op, s));
+            if (!(op->hscal->rho < op->hscal->bnorm2)) zero_start = true;
+        }
+    }
+    if (zero_start) {
+        SOP_HIP(launch_fill_zero(X, vb, s));
+        SOP_HIP(launch_cast(dt, dt, B, r, n, s));
+        SOP_HIP(launch_dot(dt, r, r, n, op->partials, op->scal, &op->scal->rho, s));
+    }
     // each step: x += alpha p (previous step) and p = r + beta p; q = N p and
     // alpha = rho / <p, q>; r -= alpha q, rho and the stopping test
-    for (;;) {
-        for (int c = 0; c < check_every; ++c) {
-            SOP_HIP(launch_sop_pstep(dt, X, p, r, n, op->scal, s));
-            SOP_TRY(sop_normal(op, di, p, q, POST_ALPHA, nullptr, true, s));
-            SOP_HIP(launch_cg_update(dt, nullptr, r, p, q, n, op->partials, op->scal, s));
+    auto run = [&](int budget, int* done, int* iters) -> cta_status {
+        SOP_HIP(launch_fill_zero(p, vb, s));
+        SOP_HIP(launch_cg_setup(op->scal, rtol * rtol, budget, s, 0));
+        for (;;) {
+            for (int c = 0; c < check_every; ++c) {
+                SOP_HIP(launch_sop_pstep(dt, X, p, r, n, op->scal, s));
+                SOP_TRY(sop_normal(op, di, p, q, POST_ALPHA, nullptr, true, s));
+                SOP_HIP(launch_cg_update(dt, nullptr, r, p, q, n, op->partials, op->scal, s));
+            }
+            SOP_TRY(read_scal(op, s));
+            if (op->hscal->done != DONE_RUNNING) break;
         }
+        SOP_HIP(launch_x_flush(dt, X, p, n, op->scal, s));
+        *done = op->hscal->done;
+        *iters = op->hscal->iters;
+        return CTA_OK;
+    };
+    // true residual ||B - N X|| in the solve's precision; leaves r = B - N X
+    // and its squared norm in scal->rho (the start of a restart)
+    auto true_res = [&](double* rel) -> cta_status {
+        SOP_TRY(sop_normal(op, di, X, q, POST_NONE, nullptr, false, s));
+        SOP_HIP(launch_residual(dt, dt, B, q, r, n, op->partials, op->scal, &op->scal->rho, s));
         SOP_TRY(read_scal(op, s));
-        if (op->hscal->done != DONE_RUNNING) break;
+        const double bn2 = op->hscal->bnorm2;
+        *rel = bn2 > 0 ? std::sqrt(op->hscal->rho / bn2) : std::sqrt(op->hscal->rho);
+        return CTA_OK;
+    };
+    int done = 0, iters = 0;
+    SOP_TRY(run(max_iter, &done, &iters));
+    int total = iters;
+    double rel_rec = std::sqrt(std::max(0.0, op->hscal->rho) / std::max(op->hscal->bnorm2, 1e-300));
+    double rel_true = 0;
+    SOP_TRY(true_res(&rel_true));
+    // one restart from the recomputed residual when the recursive residual met
+    // the tolerance but the true one did not
+    if (done == DONE_CONVERGED && rel_true > rtol && total < max_iter) {
+        SOP_TRY(run(max_iter - total, &done, &iters));
+        total += iters;
+        rel_rec = std::sqrt(std::max(0.0, op->hscal->rho) / std::max(op->hscal->bnorm2, 1e-300));
+        SOP_TRY(true_res(&rel_true));
     }
-    SOP_HIP(launch_x_flush(dt, X, p, n, op->scal, s));
-    const int done = op->hscal->done;
-    const double bn2 = op->hscal->bnorm2;
-    info->iters = op->hscal->iters;
-    info->rel_res_recursive = std::sqrt(std::max(0.0, op->hscal->rho) / std::max(bn2, 1e-300));
-    // true residual ||B - N X|| in the solve's precision
-    SOP_TRY(sop_normal(op, di, X, q, POST_NONE, nullptr, false, s));
-    SOP_HIP(launch_residual(dt, dt, B, q, r, n, op->partials, op->scal, &op->scal->dot, s));
-    SOP_TRY(read_scal(op, s));
-    info->rel_res_true = bn2 > 0 ? std::sqrt(op->hscal->dot / bn2) : std::sqrt(op->hscal->dot);
+    if (done == DONE_CONVERGED && rel_true > rtol) done = DONE_MAXITER;
+    info->iters = total;
+    info->rel_res_recursive = rel_rec;
+    info->rel_res_true = rel_true;
     info->refine_steps = 0;
     cta_status st = CTA_OK;
     if (done == DONE_BREAKDOWN)
-        st = CTA_ERR_BREAKDOWN;
+        st = fail(CTA_ERR_BREAKDOWN, "CG breakdown: <p, N p> <= 0 or a non-finite scalar");
     else if (done != DONE_CONVERGED)
-        st = CTA_NOT_CONVERGED;
+        st = fail(CTA_NOT_CONVERGED, "tolerance not reached within the iteration limit");
     info->status = st;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;

@@ -114,6 +114,13 @@ def test_no_regulariser_and_bad_sites():
 
 @pytest.mark.parametrize("chain,rtol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_cg_solve_judged_by_oracle(chain, rtol):
+    """The solve is judged by the oracle's FP64 residual (a restart from the
+    recomputed residual makes the true residual meet rtol), and its iteration
+    count is held within 10% of the oracle's CG under the same storage
+    precision: FP64 vectors for the FP64 solve, FP32 vectors with FP64 dots for
+    the FP32 solve (the oracle's storage model).  At kappa ~ 1.4e4 FP32
+    rounding alone costs this problem about 25% more iterations than FP64
+    (218 against ~275), which the storage model reproduces."""
     torch = torch_cuda()
     n = (16, 14, 12, 10)
     p = workload.scattered_problem(n, 20000, 1e-2, 0.01, seed=33, rtol=rtol, clustered=0.3)
@@ -125,13 +132,32 @@ def test_cg_solve_judged_by_oracle(chain, rtol):
     assert info["status"] == 0, info
     Xh = host(X)
     res = np.linalg.norm((B - ref(Xh)).ravel()) / np.linalg.norm(B.ravel())
-    # FP32: the recursive residual drifts from the true one by rounding
-    assert res <= (1.01 if chain == "f64" else 3.0) * rtol, res
-    # FP64: the same number of iterations as the oracle's CG within a few
-    # (FP32 loses orthogonality of the residuals and takes more)
-    if chain == "f64":
-        ocg = oracle.cg(ref, B, rtol=rtol, max_iter=5000)
-        assert abs(info["iters"] - ocg.iters) <= max(3, ocg.iters // 20), (info["iters"], ocg.iters)
+    assert res <= 1.01 * rtol, res
+    ocg = oracle.cg(ref, B, rtol=rtol, max_iter=5000, store=None if chain == "f64" else np.float32)
+    print(chain, "gpu iterations", info["iters"], "oracle", ocg.iters)
+    assert abs(info["iters"] - ocg.iters) <= max(3, ocg.iters // 10), (info["iters"], ocg.iters)
+
+
+def test_cg_solve_from_a_given_start():
+    """x0_given: a start near the solution finishes in fewer iterations;
+    fallback_zero replaces a start worse than zero."""
+    torch = torch_cuda()
+    n = (12, 10, 9)
+    p = workload.scattered_problem(n, 6000, 1e-2, 0.01, seed=34, rtol=1e-10)
+    ref = sc.ScatteredOperator(p.coords, n, p.D, p.lam)
+    B = ref.rhs(ref.forward(p.X_true) + p.noise)
+    op = cta.ScatteredOperator(p.coords, n, p.D, p.lam)
+    Bd = dev(B, torch.float64)
+    X0, info0 = op.solve(Bd, rtol=1e-10, max_iter=5000)
+    near = X0 + 1e-6 * dev(np.random.default_rng(5).standard_normal(n), torch.float64)
+    X1, info1 = op.solve(Bd, near.clone(), rtol=1e-10, max_iter=5000, x0_given=1)
+    assert info1["status"] == 0 and info1["iters"] < info0["iters"]
+    assert oracle.relative_residual(host(X1), B, ref) <= 1.01e-10
+    bad = 1e3 * dev(np.random.default_rng(6).standard_normal(n), torch.float64)
+    X2, info2 = op.solve(Bd, bad.clone(), rtol=1e-10, max_iter=5000, x0_given=1, fallback_zero=1)
+    # the same solve from zero (the LDS sums' order may move an iteration)
+    assert info2["status"] == 0 and abs(info2["iters"] - info0["iters"]) <= 2
+    assert oracle.relative_residual(host(X2), B, ref) <= 1.01e-10
 
 
 def test_application_size_sampled():
