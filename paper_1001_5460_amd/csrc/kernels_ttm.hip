@@ -340,8 +340,20 @@ __global__ __launch_bounds__(CTA_WG) __attribute__((amdgpu_waves_per_eu(3))) voi
 }
 
 
+// Variant 6: the pipelined pass with the column-affine epilogue
+// (normal_last_pipe6); same tiles, LDS and registers budget.
+__global__ __launch_bounds__(CTA_WG) __attribute__((amdgpu_waves_per_eu(3))) void k_normal_last_pipe6(
+    StridedArgs a, StencilArgs<float> st, const int* done) {
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[4];
+    double dot = 0.0;
+    normal_last_pipe6(a, smem, st, dot, xcd_logical_block(blockIdx.x, gridDim.x), gridDim.x);
+    block_partial(dot, st.partials, red);
+}
+
 static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int* grid_out, const int* done,
-                               hipStream_t s) {
+                               hipStream_t s, bool colaff = false) {
     const int N = st.order;
     const int nN = (int)st.ext[N - 1];
     if (a.kpad != 128 || a.K != a.J || a.trail % PIPE_TN != 0 || nN % 4 != 0 ||
@@ -364,6 +376,12 @@ static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int*
     int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);
     grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
     *grid_out = grid;
+    if (colaff) {
+        hipError_t e = ensure_lds(k_normal_last_pipe6, lds);
+        if (e != hipSuccess) return e;
+        k_normal_last_pipe6<<<grid, CTA_WG, lds, s>>>(a, st, done);
+        return hipGetLastError();
+    }
     hipError_t e = ensure_lds(k_normal_last_pipe, lds);
     if (e != hipSuccess) return e;
     k_normal_last_pipe<<<grid, CTA_WG, lds, s>>>(a, st, done);
@@ -468,10 +486,11 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
         }
         variant = 2;
     }
-    // variant 5: persistent and pipelined (BF16 chains, 96 < K <= 128)
-    if (variant == 5) {
+    // variants 5 and 6: persistent and pipelined (BF16 chains, 96 < K <= 128);
+    // 6 with the column-affine epilogue
+    if (variant == 5 || variant == 6) {
         if constexpr (sizeof(Tvec) == 4 && sizeof(Tc) == 2) {
-            const hipError_t e = go_last_pipe(a, st, grid, done, s);
+            const hipError_t e = go_last_pipe(a, st, grid, done, s, variant == 6);
             if (e != hipErrorNotSupported) return e;
         }
         variant = 2;

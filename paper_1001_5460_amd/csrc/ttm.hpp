@@ -907,6 +907,195 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
 }
 
 // ---------------------------------------------------------------------------
+// Variant 6 of the pipelined last pass: the same tiles, prefetch and MFMA as
+// normal_last_pipe, with a column-affine epilogue.  Thread (cg, rg) = (tid % 8,
+// tid / 8) owns the 4 columns 4 cg .. 4 cg + 3 of the tile and the 4 rows
+// 4 rg .. 4 rg + 3.  The mode indices of its columns, the band rows of the
+// middle modes and of mode N, and the gather offsets are formed once per tile
+// (they do not depend on the row), the mode-1 taps of its 4 rows come from one
+// window of 8 LDS rows, and the middle-mode gathers of row j + 1 are those of
+// row j one mode-1 stride further.  Every element's sums are the same as
+// normal_last_pipe's, in the same order (identical Q).
+__device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned char* smem,
+                                                  const StencilArgs<float>& st, double& dot_acc,
+                                                  int64_t first, int64_t step) {
+    typedef MT<bf16> T;
+    typedef float Tv;
+    typedef floatx4 vt;
+    constexpr int KPAD = 128;
+    constexpr int TN = PIPE_TN, H = PIPE_H, LDP = PIPE_LDP;
+    constexpr int E = 4, LDQ = TN + E;
+    constexpr int ldx = KPAD + 8;
+    constexpr int JT = 2, CT = 2;
+    constexpr int RPT = 4;                       // rows per thread
+    const int K = a.K;
+    const int trail = (int)a.trail;
+    const int N = st.order;
+    const int nN = (int)st.ext[N - 1];
+    constexpr size_t a_bytes = ((size_t)(TN * ldx * 2) > (size_t)(KPAD * LDQ * 4) ? (size_t)(TN * ldx * 2)
+                                                                                    : (size_t)(KPAD * LDQ * 4));
+    bf16* Xs = reinterpret_cast<bf16*>(smem);
+    float* Qs = reinterpret_cast<float*>(smem);
+    float* Pw = reinterpret_cast<float*>(smem + (a_bytes + 15) / 16 * 16);
+    float* band1 = Pw + (size_t)KPAD * LDP;
+    float* bandN = band1 + (size_t)KPAD * 5;
+    const bool has1 = st.rband[0] != nullptr;
+    const bool hasN = st.rband[N - 1] != nullptr;
+    float* __restrict__ Q = reinterpret_cast<float*>(a.Y);
+    const float* __restrict__ P = st.P;
+    const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
+    if (has1)
+        for (int u = threadIdx.x; u < K * 5; u += CTA_WG) band1[u] = st.rband[0][u];
+    if (hasN)
+        for (int u = threadIdx.x; u < nN * 5; u += CTA_WG) bandN[u] = st.rband[N - 1][u];
+    const int cpp = (int)(a.plane / TN), per = cpp * a.pgroup;
+    const float inv_per = a.pgroup > 0 ? 1.0f / (float)per : 0.f;
+    const float inv_pg = a.pgroup > 0 ? 1.0f / (float)a.pgroup : 0.f;
+    auto tcol = [&](int64_t tl) -> int {
+        const int t = (int)tl;
+        if (a.pgroup <= 0) return t * TN;
+        const int grp = small_div(t, per, inv_per), rr = t - grp * per;
+        const int c = small_div(rr, a.pgroup, inv_pg), ig = rr - c * a.pgroup;
+        return (grp * a.pgroup + ig) * (int)a.plane + c * TN;
+    };
+    const int cg = threadIdx.x & 7, rg = threadIdx.x >> 3;
+    const int c = cg * E;
+    const int j0 = rg * RPT;
+    PipeRegs r;
+    if (first < a.ntiles) pipe_load<KPAD>(a, P, tcol(first), K, r);
+    const Tv lam = (Tv)st.lam;
+    for (int64_t tile = first; tile < a.ntiles; tile += step) {
+        const int t0 = tcol(tile);
+        const int t = t0 + c;
+        pipe_store<KPAD>(r, Xs, Pw, K);
+        __syncthreads();
+        // ---- middle-mode regulariser taps (rows past J read row J-1, unused) ----
+        vt rmid[RPT];
+#pragma unroll
+        for (int w = 0; w < RPT; ++w)
+#pragma unroll
+            for (int e = 0; e < E; ++e) rmid[w][e] = Tv(0);
+        for (int k = 1; k < N - 1; ++k) {
+            const Tv* __restrict__ rb = st.rband[k];
+            if (!rb) continue;
+            const int sk = (int)st.stride[k], nk = (int)st.ext[k];
+            const int u = fast_div(t, st.smul[k], st.sshift[k]);
+            const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
+            const Tv* br = rb + ik * 5;
+            const Tv b0 = br[0], b1 = br[1], b2 = br[2], b3 = br[3], b4 = br[4];
+            int off[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
+                off[q] = ((ik + d >= 0 && ik + d < nk) ? d : 0) * sk;
+            }
+#pragma unroll
+            for (int w = 0; w < RPT; ++w) {
+                const int j = min(j0 + w, a.J - 1);
+                const vt pc = *reinterpret_cast<const vt*>(Pw + j * LDP + H + c);
+                const Tv* __restrict__ pb = P + (int64_t)j * trail + t;
+                vt nbv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) nbv[q] = *reinterpret_cast<const vt*>(pb + off[q]);
+                rmid[w] += b2 * pc;
+                rmid[w] += b0 * nbv[0];
+                rmid[w] += b1 * nbv[1];
+                rmid[w] += b3 * nbv[2];
+                rmid[w] += b4 * nbv[3];
+            }
+        }
+        // ---- MFMA (as normal_last_pipe) ----
+        {
+            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            const int jb = wave * JT * 16;
+            const int g = lane >> 4, l16 = lane & 15;
+            typename T::acc acc[JT][CT];
+#pragma unroll
+            for (int x = 0; x < JT; ++x)
+#pragma unroll
+                for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
+            mfma_cols<bf16, JT, CT>(Xs, ldx, M, a.ldm, 0, jb, KPAD, acc);
+            if (tile + step < a.ntiles) pipe_load<KPAD>(a, P, tcol(tile + step), K, r);
+            __syncthreads();  // Xs is dead; its space becomes Qs
+#pragma unroll
+            for (int x = 0; x < JT; ++x) {
+                const int j = jb + x * 16 + l16;
+                if (j >= a.J) continue;
+#pragma unroll
+                for (int y = 0; y < CT; ++y) {
+                    vt o;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) o[q] = acc[x][y][q];
+                    *reinterpret_cast<vt*>(Qs + j * LDQ + y * 16 + 4 * g) = o;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- epilogue: modes 1 and N from the LDS window ----
+        if (j0 < a.J) {
+            // mode-1 taps: a rolling window of 5 rows (clamped; out-of-range taps
+            // have zero band coefficients)
+            auto prow_at = [&](int jj) -> vt {
+                jj = min(max(jj, 0), K - 1);
+                return *reinterpret_cast<const vt*>(Pw + jj * LDP + H + c);
+            };
+            vt wm2 = prow_at(j0 - 2), wm1 = prow_at(j0 - 1), w0 = prow_at(j0), w1 = prow_at(j0 + 1);
+            // mode-N band rows of the 4 columns: 20 consecutive floats (i0 % 4 == 0)
+            const int i0 = hasN ? t - fast_div(t, st.emul[N - 1], st.eshift[N - 1]) * nN : 0;
+#pragma unroll
+            for (int w = 0; w < RPT; ++w) {
+                const int j = j0 + w;
+                if (j >= a.J) break;
+                const vt w2 = prow_at(j + 2);
+                const vt pc = w0;
+                vt s = *reinterpret_cast<const vt*>(Qs + j * LDQ + c);  // chain part, lam applied below
+                vt reg = rmid[w];
+                if (has1) {
+                    const Tv* b1 = band1 + j * 5;
+                    reg += b1[0] * wm2;
+                    reg += b1[1] * wm1;
+                    reg += b1[2] * w0;
+                    reg += b1[3] * w1;
+                    reg += b1[4] * w2;
+                }
+                if (hasN) {
+                    Tv bN[E * 5];
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        const vt v = *reinterpret_cast<const vt*>(bandN + i0 * 5 + 4 * q);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) bN[4 * q + e] = v[e];
+                    }
+                    Tv wv[3 * E];
+                    const Tv* prow = Pw + j * LDP + H + c;
+                    const vt pl = *reinterpret_cast<const vt*>(prow - E);
+                    const vt pr = *reinterpret_cast<const vt*>(prow + E);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        wv[e] = pl[e];
+                        wv[E + e] = pc[e];
+                        wv[2 * E + e] = pr[e];
+                    }
+#pragma unroll
+                    for (int e = 0; e < E; ++e)
+#pragma unroll
+                        for (int d = -2; d <= 2; ++d) reg[e] += bN[e * 5 + d + 2] * wv[E + e + d];
+                }
+                const vt qv = s + lam * reg;
+                *reinterpret_cast<vt*>(Q + (int64_t)j * trail + t) = qv;
+#pragma unroll
+                for (int e = 0; e < E; ++e) dot_acc += (double)pc[e] * (double)qv[e];
+                wm2 = wm1;
+                wm1 = w0;
+                w0 = w1;
+                w1 = w2;
+            }
+        }
+        __syncthreads();  // LDS is reused by the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Last pass in row blocks (FP32 vectors, tensor order 3 or 4): a tile is 32
 // output rows x 32 columns, and everything the 17-point stencil reads is staged
 // in LDS with coalesced loads: P rows j0-2 .. j0+33 over the columns
