@@ -115,6 +115,23 @@ cta_status cta_ttm(int order, const int64_t* x_dims, const void* X, cta_dtype x_
                    cta_dtype compute, void* Y, cta_dtype y_dtype, void* workspace,
                    size_t workspace_bytes, void* stream);
 
+/* cta_ttm without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace (padded factor copies and
+ * the chain intermediates, the bytes cta_ttm_workspace_bytes reports) comes
+ * from a fixed array of CTA_TTM_SCRATCH_BYTES in the library's device memory,
+ * one per GPU, held until the process ends; products that need more return
+ * CTA_ERR_SHAPE.  No call allocates or frees memory.  Every call on one GPU
+ * uses that GPU's array, so calls that overlap on one GPU (two streams, two
+ * host threads) race and must be serialised by the caller; the array keeps
+ * the last call's contents, which no later call reads before writing.
+ * Arguments, results and errors otherwise as cta_ttm; asynchronous. */
+#define CTA_TTM_SCRATCH_BYTES (32u << 20)
+cta_status cta_ttm_noalloc(int order, const int64_t* x_dims, const void* X, cta_dtype x_dtype,
+                           uint32_t mode_mask, uint32_t trans_mask, const void* const* M,
+                           const int64_t* m_rows, const int64_t* m_cols, cta_dtype m_dtype,
+                           cta_dtype compute, void* Y, cta_dtype y_dtype, void* stream);
+
 /* ------------------------------------------------------------------------
  * Operator handle: the per-mode factors of one tensor equation.
  *

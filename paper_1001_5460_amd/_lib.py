@@ -61,6 +61,9 @@ _SIGS = {
     "cta_ttm": (ctypes.c_int, [ctypes.c_int, _I64P, _P, ctypes.c_int, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.POINTER(_P), _I64P, _I64P, ctypes.c_int,
                                ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_size_t, _P]),
+    "cta_ttm_noalloc": (ctypes.c_int, [ctypes.c_int, _I64P, _P, ctypes.c_int, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.POINTER(_P), _I64P, _I64P, ctypes.c_int,
+                                       ctypes.c_int, _P, ctypes.c_int, _P]),
     "cta_op_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _I64P, _I64P,
                                      ctypes.POINTER(_P), ctypes.POINTER(_P), _I64P,
                                      ctypes.c_double, _P]),
@@ -262,6 +265,42 @@ def cta_ttm(X, mats, trans=(), compute="f32", out=None, out_dtype=None, stream=N
     _check(lib.cta_ttm(order, _i64(X.shape), _dev(X, "X"), _dt(X), mask, tmask, ptrs,
                        _i64(rows), _i64(cols), mdt, cdt, _dev(out, "out"), _dt(out),
                        ctypes.c_void_p(aligned), ws_bytes, _stream(stream)))
+    return out
+
+
+def cta_ttm_noalloc(X, mats, trans=(), compute="f32", out=None, out_dtype=None, stream=None):
+    """As cta_ttm, with the library's fixed scratch instead of a workspace (no allocation
+    inside the library; ``out`` is allocated here only when not given)."""
+    torch = _torch()
+    lib = load_library()
+    order = X.dim()
+    if len(mats) != order:
+        raise CtaError(-1, "one entry per mode is required in mats")
+    mask, tmask = 0, 0
+    rows, cols = [0] * order, [0] * order
+    ptrs = (ctypes.c_void_p * order)()
+    out_shape = list(X.shape)
+    m_dtype = None
+    for k, M in enumerate(mats):
+        if M is None:
+            continue
+        mask |= 1 << k
+        if m_dtype is None:
+            m_dtype = M.dtype
+        elif M.dtype != m_dtype:
+            raise CtaError(-3, "all factors must share one dtype")
+        rows[k], cols[k] = M.shape
+        ptrs[k] = _dev(M, f"mats[{k}]").value
+        out_shape[k] = M.shape[1] if k in trans else M.shape[0]
+        if k in trans:
+            tmask |= 1 << k
+    if out is None:
+        out = torch.empty(out_shape, dtype=out_dtype or X.dtype, device=X.device)
+    if list(out.shape) != out_shape:
+        raise CtaError(-2, f"out has shape {tuple(out.shape)}, expected {tuple(out_shape)}")
+    mdt = _dt(torch.empty(0, dtype=m_dtype)) if m_dtype is not None else F32
+    _check(lib.cta_ttm_noalloc(order, _i64(X.shape), _dev(X, "X"), _dt(X), mask, tmask, ptrs, _i64(rows),
+                               _i64(cols), mdt, _DT_NAME[compute], _dev(out, "out"), _dt(out), _stream(stream)))
     return out
 
 

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/cta.h"
@@ -75,6 +76,35 @@ extern "C" size_t cta_ttm_workspace_bytes(int order, const int64_t* x_dims, uint
     return p.total;
 }
 
+// ---------------------------------------------------------------------------
+// Fixed scratch of cta_ttm_noalloc: one array per GPU in the code object's
+// device memory, reached only through the address hipGetSymbolAddress returns
+// for the current device (the array's name in host code is not a device
+// address).  Calls on one GPU share it.
+static __device__ __align__(256) unsigned char scratch[CTA_TTM_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+cta_status scratch_for_current_device(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CTA_ERR_HIP, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices) return fail(CTA_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(CTA_ERR_HIP, "hipGetSymbolAddress of the scratch array: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CTA_OK;
+}
+}  // namespace
+
 extern "C" cta_status cta_ttm(int order, const int64_t* x_dims, const void* X, cta_dtype x_dtype,
                               uint32_t mode_mask, uint32_t trans_mask, const void* const* M,
                               const int64_t* m_rows, const int64_t* m_cols, cta_dtype m_dtype,
@@ -109,4 +139,21 @@ extern "C" cta_status cta_ttm(int order, const int64_t* x_dims, const void* X, c
     }
     return run_chain(order, p.in_ext, p.out_ext, mats, p.order, X, (int)x_dtype, Y, (int)y_dtype,
                      (int)compute, ws + p.buf_off0, ws + p.buf_off1, s);
+}
+
+extern "C" cta_status cta_ttm_noalloc(int order, const int64_t* x_dims, const void* X, cta_dtype x_dtype,
+                                      uint32_t mode_mask, uint32_t trans_mask, const void* const* M,
+                                      const int64_t* m_rows, const int64_t* m_cols, cta_dtype m_dtype,
+                                      cta_dtype compute, void* Y, cta_dtype y_dtype, void* stream) {
+    TtmPlan p;
+    cta_status st = make_plan(order, x_dims, mode_mask, trans_mask, m_rows, m_cols, compute, &p);
+    if (st != CTA_OK) return st;
+    if (p.total > (size_t)CTA_TTM_SCRATCH_BYTES)
+        return fail(CTA_ERR_SHAPE, "this product needs %zu bytes of scratch; cta_ttm_noalloc has %zu",
+                    p.total, (size_t)CTA_TTM_SCRATCH_BYTES);
+    void* ws = nullptr;
+    st = scratch_for_current_device(&ws);
+    if (st != CTA_OK) return st;
+    return cta_ttm(order, x_dims, X, x_dtype, mode_mask, trans_mask, M, m_rows, m_cols, m_dtype, compute, Y,
+                   y_dtype, ws, (size_t)CTA_TTM_SCRATCH_BYTES, stream);
 }
