@@ -280,3 +280,71 @@ def test_create_rejects_unsupported():
         cta.cta_ws_create((8, 8, 8, 8), 16, WIDTH, 1, 0)
     with pytest.raises(cta.CtaError):
         cta.cta_ws_create((8, 8, 0, 8), C, WIDTH, 1, 0)
+
+
+def _sparse_integer_params(blocks, seed, nnz=2):
+    """Parameters in {-1, 0, 1} with zero biases: lift weights +-1, every output
+    channel of every convolution has `nnz` nonzero (tap, input channel) weights,
+    projection weights +-1, so activations stay small integers."""
+    rng = np.random.default_rng(seed)
+    P = wsn.unpack(np.zeros(wsn.param_count(C, WIDTH, blocks, 4)), C, WIDTH, blocks, 4)
+    P["lw"] = rng.choice([-1.0, 1.0], C)
+    P["lb"] = np.zeros(C)
+    for b in range(blocks):
+        for k in range(4):
+            W = np.zeros((C, C, WIDTH))
+            for co in range(C):
+                for _ in range(nnz):
+                    W[co, rng.integers(C), rng.integers(WIDTH)] = rng.choice([-1.0, 1.0])
+            P["W"][b][k] = W
+            P["c"][b][k] = np.zeros(C)
+    P["pw"] = rng.choice([-1.0, 0.0, 1.0], C)
+    P["pb"] = 0.0
+    return P
+
+
+def test_integer_network_equals_exact_oracle_bit_for_bit():
+    """With integer weights in {-1, 0, 1}, zero biases, an input of +-1 entries
+    (RMS exactly 1) and a target one integer away from the output, every
+    activation is a small integer and every activation gradient an integer
+    multiple of 2^-9 (1,024 voxels), all exact in BF16; the FP32 sums of the
+    weight gradients are exact too.  So the GPU forward, loss and the whole
+    gradient must equal the exact FP64 oracle (no storage model) bit for bit
+    (App. A.8: the derivative of the loss through every layer)."""
+    torch = torch_cuda()
+    n, blocks = (8, 4, 4, 8), 2
+    P = _sparse_integer_params(blocks, seed=5)
+    rng = np.random.default_rng(6)
+    B = rng.choice([-1.0, 1.0], n)
+    out, acts = wsn.forward(P, B, keep=True)
+    # preconditions of exactness (checked on the oracle's own values)
+    for h in acts["h"]:
+        assert np.abs(h).max() <= 256 and np.array_equal(h, np.round(h))
+    for zs in acts["z"]:
+        for z in zs:
+            assert np.abs(z).max() <= 256 and np.array_equal(z, np.round(z))
+    T = out + rng.choice([-1.0, 0.0, 1.0], n)
+    L_ref, g_ref = wsn.mse_loss(P, B, T)
+    # every stored activation and activation gradient is exact in BF16: the
+    # storage model gives the exact oracle's loss and gradient
+    L_st, g_st = wsn.mse_loss(P, B, T, store=wsn.bf16_round)
+    assert L_st == L_ref and np.array_equal(g_st, g_ref)
+    h = cta.cta_ws_create(n, C, WIDTH, blocks, 0)
+    try:
+        cta.cta_ws_params(h, wsn.pack(P).astype(np.float32), set=1)
+        Bd, Td = dev(B, torch.float32), dev(T, torch.float32)
+        X0, dX0 = torch.empty_like(Bd), torch.empty_like(Bd)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        cta.cta_ws_zero_grad(h)
+        cta.cta_ws_forward(h, Bd, X0, training=True)
+        cta.cta_ws_mse(h, X0, Td, dX0, loss)
+        cta.cta_ws_backward(h, dX0)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(X0), out)
+        assert float(loss.item()) == L_ref
+        g_gpu = cta.cta_ws_params(h, set=2).astype(np.float64)
+        bad = np.nonzero(g_gpu != g_ref)[0]
+        assert bad.size == 0, (bad.size, bad[:5], g_gpu[bad[:5]], g_ref[bad[:5]])
+        assert np.count_nonzero(g_ref) > 0.2 * g_ref.size   # the gradient is not trivially zero
+    finally:
+        cta.cta_ws_destroy(h)

@@ -184,3 +184,32 @@ def test_adam_second_and_third_steps_by_hand():
     assert np.isclose(m[0], 1.125) and np.isclose(v[0], 2.453125)
     th3 = th2 - 0.1 * (1.125 / 0.875) / np.sqrt(2.453125 / 0.578125)
     assert np.isclose(th[0], th3, rtol=1e-14)
+
+
+def test_what_a_start_can_save_on_the_blob_workload():
+    """How much any starting tensor that captures the solution's structure can
+    save on the warm-start workload (blob fields plus N(0, 0.1) white noise,
+    collocation 1.5n x n, lambda 1e-3), by the oracle's CG to 1e-8: starting
+    from the exact noise-free blob field, or from the coarse-grid projection of
+    the exact solution, saves at most a few percent of the iterations.  CG's
+    count is set by the rough (noise) part of the solution, which a start can
+    only supply by applying the inverse operator itself."""
+    import workload
+    from oracle import multigrid
+    n, m = (24, 24, 24, 8), (36, 36, 36, 12)
+    A, D = workload.factors(n, m)
+    op = oracle.NormalOperator(A, D, 1e-3)
+    rng = np.random.default_rng(10000)
+    X = workload.blob_field(n, rng, 0.1)
+    B = op.rhs(op.forward(X) + 0.01 * rng.standard_normal(m))
+    exact = oracle.cg(op, B, rtol=1e-13)
+    zero = oracle.cg(op, B, rtol=1e-8).iters
+    smooth = workload.blob_field(n, np.random.default_rng(10000), 0.0)
+    P = [multigrid.interpolation(k, (k + 1) // 2) for k in n]
+    Xc = exact.x
+    for k in range(4):
+        Xc = oracle.mode_product(Xc, np.linalg.solve(P[k].T @ P[k], P[k].T), k)
+    coarse = multigrid.prolong(Xc, P)
+    for x0 in (smooth, coarse):
+        its = oracle.cg(op, B, x0=x0, rtol=1e-8).iters
+        assert its >= 0.93 * zero, (its, zero)
