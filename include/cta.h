@@ -191,9 +191,8 @@ cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
  * blocks of 32 with the whole stencil staged on chip, F32/BF16 chains of
  * order 3 or 4, else as 2; 5: persistent workgroups that load the next
  * tile while computing the current one, BF16 chains with 96 < n_1 <= 128,
- * else as 2; 6: as 5 with each thread owning 4 columns of 4 rows in the
- * epilogue, so mode indices, band rows and gather offsets are formed once
- * per tile). */
+ * else as 2; 6: as 5 with zero rows around the LDS window and vector reads
+ * of the band coefficients). */
 cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3);
 cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3);
 

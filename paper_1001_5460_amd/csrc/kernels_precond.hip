@@ -62,7 +62,7 @@ __device__ __forceinline__ double diag_at(const DiagDesc& d, double prod, double
          i += (int64_t)gridDim.x * CTA_WG * kPer) {                                      \
         const int L_ = (d).order - 1;                                                     \
         const int cnt = (int)std::min<int64_t>(kPer, (n) - i);                            \
-        double dg[kPer];                                                                  \
+        double dg[kPer] = {1.0, 1.0, 1.0, 1.0};                                          \
         if (cnt == kPer && ((d).ext[L_] % kPer) == 0) {                                   \
             const uint32_t lead = fdiv((uint32_t)i, (d).fmul[L_], (d).fsh[L_]);           \
             double pr, sm;                                                                \
@@ -81,6 +81,30 @@ __device__ __forceinline__ double diag_at(const DiagDesc& d, double prod, double
         BODY                                                                              \
     }
 
+template <typename T> struct V4 { typedef T __attribute__((ext_vector_type(4))) type; };
+
+// 4 consecutive elements as one vector access when FULL (16 or 32 bytes,
+// aligned: i is a multiple of 4 and the arrays are allocation-aligned), else
+// element by element for the first cnt.
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type ld4(const T* p, bool full, int cnt) {
+    typename V4<T>::type v;
+    if (full) return *reinterpret_cast<const typename V4<T>::type*>(p);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = u < cnt ? p[u] : T(0);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ void st4(T* p, const typename V4<T>::type& v, bool full, int cnt) {
+    if (full) {
+        *reinterpret_cast<typename V4<T>::type*>(p) = v;
+        return;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (u < cnt) p[u] = v[u];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ z = omega r / d
@@ -91,13 +115,16 @@ __global__ __launch_bounds__(CTA_WG) void k_jacobi_apply(const T* __restrict__ r
     if (gate && *gate) return;
     __shared__ double red[4];
     double acc = 0.0;
+    const bool vec = (n % 4) == 0;
     CTA_DIAG_SWEEP(n, d, {
-        for (int u = 0; u < cnt; ++u) {
-            const double rv = (double)r[i + u];
-            const T zv = (T)(omega * rv / dg[u]);
-            z[i + u] = zv;
-            acc += rv * (double)zv;
+        const bool full = vec && cnt == kPer;
+        const typename V4<T>::type rv = ld4(r + i, full, cnt);
+        typename V4<T>::type zv;
+        for (int u = 0; u < kPer; ++u) {
+            zv[u] = (T)(omega * (double)rv[u] / dg[u]);
+            if (u < cnt) acc += (double)rv[u] * (double)zv[u];
         }
+        st4(z + i, zv, full, cnt);
     })
     if (partials) block_partial(acc, partials, red);
 }
@@ -135,15 +162,22 @@ __global__ __launch_bounds__(CTA_WG) void k_jacobi_update(T* __restrict__ r, con
     __shared__ double red[4];
     const T alpha = (T)scal->alpha;
     double rr = 0.0, rz = 0.0;
+    const bool vec = (n % 4) == 0;
     CTA_DIAG_SWEEP(n, d, {
-        for (int u = 0; u < cnt; ++u) {
-            const T rv = r[i + u] - alpha * q[i + u];
-            r[i + u] = rv;
-            const T zv = (T)((double)rv / dg[u]);
-            z[i + u] = zv;
-            rr += (double)rv * (double)rv;
-            rz += (double)rv * (double)zv;
+        const bool full = vec && cnt == kPer;
+        typename V4<T>::type rv = ld4(r + i, full, cnt);
+        const typename V4<T>::type qv = ld4(q + i, full, cnt);
+        typename V4<T>::type zv;
+        for (int u = 0; u < kPer; ++u) {
+            rv[u] = rv[u] - alpha * qv[u];
+            zv[u] = (T)((double)rv[u] / dg[u]);
+            if (u < cnt) {
+                rr += (double)rv[u] * (double)rv[u];
+                rz += (double)rv[u] * (double)zv[u];
+            }
         }
+        st4(r + i, rv, full, cnt);
+        st4(z + i, zv, full, cnt);
     })
     block_partial(rr, partials, red);
     block_partial(rz, partials2, red);
@@ -184,14 +218,20 @@ __global__ __launch_bounds__(CTA_WG) void k_jacobi_correct(const T* C, T* Cout, 
     if (gate && *gate) return;
     __shared__ double red[4];
     double acc = 0.0;
+    const bool vec = (n % 4) == 0;
     CTA_DIAG_SWEEP(n, d, {
-        for (int u = 0; u < cnt; ++u) {
-            const double b = (double)B[i + u];
-            const double res = b - (double)Q[i + u];
-            const T cv = (T)((double)C[i + u] + omega * res / dg[u]);
-            Cout[i + u] = cv;
-            acc += dotmode == 1 ? res * res : b * (double)cv;
+        const bool full = vec && cnt == kPer;
+        const typename V4<T>::type bv = ld4(B + i, full, cnt);
+        const typename V4<T>::type qv = ld4(Q + i, full, cnt);
+        const typename V4<T>::type cv0 = ld4(C + i, full, cnt);
+        typename V4<T>::type cv;
+        for (int u = 0; u < kPer; ++u) {
+            const double b = (double)bv[u];
+            const double res = b - (double)qv[u];
+            cv[u] = (T)((double)cv0[u] + omega * res / dg[u]);
+            if (u < cnt) acc += dotmode == 1 ? res * res : b * (double)cv[u];
         }
+        st4(Cout + i, cv, full, cnt);
     })
     if (dotmode) block_partial(acc, partials, red);
 }

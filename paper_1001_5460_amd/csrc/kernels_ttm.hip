@@ -68,7 +68,39 @@ static hipError_t go_strided(StridedArgs a, const int* done, hipStream_t s) {
 // only vector-memory loads of a tile are its successor's.  Same sums, in the
 // same order, as strided_tile with JT = 2, WJ = 4, CT = 4.
 constexpr int SPIPE_TN = 64;
-constexpr int SPIPE_LD = 128 + 8;   // LDS pitch (bf16) of the factor rows and X columns
+constexpr int SPIPE_LD = 128 + 8;   // LDS pitch (bf16) of the factor rows
+constexpr int SPIPE_XLD = 128;      // LDS pitch (bf16) of the X columns
+
+// An X tile sits in LDS as [64 columns t][128 K values] (zero past K), with the
+// sixteen 16-byte chunks of column t permuted by XOR with xs_swz(t).  A wave's
+// transposing stores (one K pair of the 8 columns t = 8 cg + c, fixed c) and
+// the fragment reads (16 lanes, 16 consecutive columns, one chunk each) then
+// both touch 64 distinct banks.
+__device__ __forceinline__ int xs_swz(int t) { return 2 * ((t & 7) ^ (t >> 3)) + ((t >> 3) & 1); }
+
+// Registers of spipe_load -> the swizzled X tile.
+__device__ __forceinline__ void xs_store(bf16* Xs, const bf16x8 (&r)[4]) {
+    typedef bf16 __attribute__((ext_vector_type(2))) bf16x2;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int u = threadIdx.x + CTA_WG * i;
+        const int cg = u & 7, kp = u >> 3;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int t = cg * 8 + c;
+            bf16x2 pr;
+            pr[0] = r[2 * i][c];
+            pr[1] = r[2 * i + 1][c];
+            *reinterpret_cast<bf16x2*>(Xs + t * SPIPE_XLD + (((kp >> 2) ^ xs_swz(t)) << 3) + 2 * (kp & 3)) = pr;
+        }
+    }
+}
+
+// The 8 K values [8 chunk, 8 chunk + 8) of column t.
+template <typename F>
+__device__ __forceinline__ F xs_frag(const bf16* Xs, int t, int chunk) {
+    return *reinterpret_cast<const F*>(Xs + t * SPIPE_XLD + ((chunk ^ xs_swz(t)) << 3));
+}
 
 __device__ __forceinline__ void spipe_load(const StridedArgs& a, int64_t tile, bf16x8 (&r)[4]) {
     const bf16* __restrict__ X = reinterpret_cast<const bf16*>(a.X);
@@ -97,7 +129,7 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
     constexpr int JT = 2, CT = 4, VEC = T::VEC;
     extern __shared__ __align__(16) unsigned char smem[];
     bf16* Ms = reinterpret_cast<bf16*>(smem);                 // [128][SPIPE_LD]
-    bf16* Xs = Ms + 128 * SPIPE_LD;                            // [64][SPIPE_LD]
+    bf16* Xs = Ms + 128 * SPIPE_LD;                            // [64][SPIPE_XLD], swizzled
     const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
     // the factor, zero outside J x K
     for (int u = threadIdx.x; u < 128 * 16; u += CTA_WG) {
@@ -116,20 +148,7 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
     const int jb = wave * JT * 16;
     bf16* __restrict__ Y = reinterpret_cast<bf16*>(a.Y);
     for (int64_t tile = first; tile < a.ntiles; tile += step) {
-        // registers -> Xs[t][k]
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int u = threadIdx.x + CTA_WG * i;
-            const int cg = u & 7, kp = u >> 3;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                typedef bf16 __attribute__((ext_vector_type(2))) bf16x2;
-                bf16x2 pr;
-                pr[0] = r[2 * i][c];
-                pr[1] = r[2 * i + 1][c];
-                *reinterpret_cast<bf16x2*>(Xs + (cg * 8 + c) * SPIPE_LD + 2 * kp) = pr;
-            }
-        }
+        xs_store(Xs, r);
         __syncthreads();
         if (tile + step < a.ntiles) spipe_load(a, tile + step, r);
         typename T::acc acc[JT][CT];
@@ -142,8 +161,7 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
             const int k0 = ks * T::KSTEP + VEC * g;
             typename T::frag xa[CT], mb[JT];
 #pragma unroll
-            for (int y = 0; y < CT; ++y)
-                xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (y * 16 + l16) * SPIPE_LD + k0);
+            for (int y = 0; y < CT; ++y) xa[y] = xs_frag<typename T::frag>(Xs, y * 16 + l16, k0 >> 3);
 #pragma unroll
             for (int x = 0; x < JT; ++x)
                 mb[x] = *reinterpret_cast<const typename T::frag*>(Ms + (jb + x * 16 + l16) * SPIPE_LD + k0);
@@ -178,7 +196,7 @@ static hipError_t go_strided_pipe(StridedArgs a, const int* done, hipStream_t s)
     a.ntiles = a.lead * a.ntt;
     if (a.ntiles >= ((int64_t)1 << 30)) return hipErrorNotSupported;
     fastdiv_init((uint32_t)a.ntt, &a.tmul, &a.tshift);
-    const size_t lds = (size_t)(128 + SPIPE_TN) * SPIPE_LD * sizeof(bf16);
+    const size_t lds = ((size_t)128 * SPIPE_LD + (size_t)SPIPE_TN * SPIPE_XLD) * sizeof(bf16);
     hipError_t e = ensure_lds(k_strided_pipe, lds);
     if (e != hipSuccess) return e;
     int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);
@@ -340,15 +358,23 @@ __global__ __launch_bounds__(CTA_WG) __attribute__((amdgpu_waves_per_eu(3))) voi
 }
 
 
-// Variant 6: the pipelined pass with the column-affine epilogue
-// (normal_last_pipe6); same tiles, LDS and registers budget.
+// Variant 6: the pipelined pass with fewer LDS and vector instructions per
+// item (normal_last_pipe6); LDS: 4 more window rows and 3 more floats per
+// mode-1 band row.
 __global__ __launch_bounds__(CTA_WG) __attribute__((amdgpu_waves_per_eu(3))) void k_normal_last_pipe6(
     StridedArgs a, StencilArgs<float> st, const int* done) {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4];
     double dot = 0.0;
-    normal_last_pipe6(a, smem, st, dot, xcd_logical_block(blockIdx.x, gridDim.x), gridDim.x);
+    int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x, end = a.ntiles;
+    if (a.xsweep) {
+        const int64_t per = (a.ntiles + CTA_XCDS - 1) / CTA_XCDS, x = blockIdx.x % CTA_XCDS;
+        step = gridDim.x / CTA_XCDS;
+        first = x * per + blockIdx.x / CTA_XCDS;
+        end = min((x + 1) * per, a.ntiles);
+    }
+    normal_last_pipe6(a, smem, st, dot, first, step, end);
     block_partial(dot, st.partials, red);
 }
 
@@ -357,7 +383,8 @@ static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int*
     const int N = st.order;
     const int nN = (int)st.ext[N - 1];
     if (a.kpad != 128 || a.K != a.J || a.trail % PIPE_TN != 0 || nN % 4 != 0 ||
-        a.trail / PIPE_TN >= (int64_t(1) << 22))   // tile columns from float reciprocals
+        a.trail / PIPE_TN >= (int64_t(1) << 22) ||   // tile columns from float reciprocals
+        (uint64_t)a.K * (uint64_t)a.trail * sizeof(float) >= (uint64_t(1) << 32))   // 32-bit offsets into P
         return hipErrorNotSupported;
     a.ntt = a.trail / PIPE_TN;
     a.ntiles = a.ntt;
@@ -369,8 +396,11 @@ static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int*
         a.nplane = nplane;
         a.pgroup = 8;
     }
+    a.xsweep = 0;
     const size_t xq = std::max<size_t>((size_t)PIPE_TN * (128 + 8) * 2, (size_t)128 * (PIPE_TN + 4) * 4);
-    const size_t lds = (xq + 15) / 16 * 16 + (size_t)128 * PIPE_LDP * 4 + (size_t)(128 + nN) * 5 * 4;
+    const size_t lds = colaff ? (xq + 15) / 16 * 16 + (size_t)(128 + 4) * PIPE_LDP * 4 + (size_t)128 * 8 * 4 +
+                                    (size_t)nN * 5 * 4
+                              : (xq + 15) / 16 * 16 + (size_t)128 * PIPE_LDP * 4 + (size_t)(128 + nN) * 5 * 4;
     if (lds > 64 * 1024) return hipErrorNotSupported;
     // persistent grid: three workgroups per CU, a multiple of the XCD count
     int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);
@@ -439,6 +469,7 @@ static hipError_t go_last_js(StridedArgs a, const StencilArgs<float>& st, int* g
         a.nplane = gm.nF;
         a.pgroup = 8;
     }
+    a.xsweep = 0;
     const int grid = (grid_for(a.ntiles, kMaxGrid) + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
     *grid_out = grid;
     hipError_t e;
@@ -558,19 +589,7 @@ __global__ __launch_bounds__(CTA_WG) void k_last_nr_pipe(StridedArgs a, const fl
     float* __restrict__ Z = reinterpret_cast<float*>(a.Y);
     double dot = 0.0;
     for (int64_t tile = first; tile < a.ntiles; tile += step) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int u = threadIdx.x + CTA_WG * i;
-            const int cg = u & 7, kp = u >> 3;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                typedef bf16 __attribute__((ext_vector_type(2))) bf16x2;
-                bf16x2 pr;
-                pr[0] = r[2 * i][c];
-                pr[1] = r[2 * i + 1][c];
-                *reinterpret_cast<bf16x2*>(Xs + (cg * 8 + c) * SPIPE_LD + 2 * kp) = pr;
-            }
-        }
+        xs_store(Xs, r);
         __syncthreads();
         // R of this tile's outputs (rows past J read row J-1 and are not used)
         const int64_t t0 = tile * SPIPE_TN;
@@ -593,8 +612,7 @@ __global__ __launch_bounds__(CTA_WG) void k_last_nr_pipe(StridedArgs a, const fl
             const int k0 = ks * T::KSTEP + VEC * g;
             typename T::frag xa[CT], mb[JT];
 #pragma unroll
-            for (int y = 0; y < CT; ++y)
-                xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (y * 16 + l16) * SPIPE_LD + k0);
+            for (int y = 0; y < CT; ++y) xa[y] = xs_frag<typename T::frag>(Xs, y * 16 + l16, k0 >> 3);
 #pragma unroll
             for (int x = 0; x < JT; ++x)
                 mb[x] = *reinterpret_cast<const typename T::frag*>(Ms + (jb + x * 16 + l16) * SPIPE_LD + k0);
@@ -633,7 +651,7 @@ hipError_t launch_last_nr(const void* X, void* Z, const void* R, const Mat& M, i
     a.ntiles = a.ntt;
     if (a.ntiles >= ((int64_t)1 << 30)) return hipErrorNotSupported;
     fastdiv_init((uint32_t)a.ntt, &a.tmul, &a.tshift);   // spipe_load: tile / ntt (= 0 here)
-    const size_t lds = (size_t)(128 + SPIPE_TN) * SPIPE_LD * sizeof(bf16);
+    const size_t lds = ((size_t)128 * SPIPE_LD + (size_t)SPIPE_TN * SPIPE_XLD) * sizeof(bf16);
     hipError_t e = ensure_lds(k_last_nr_pipe, lds);
     if (e != hipSuccess) return e;
     int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);

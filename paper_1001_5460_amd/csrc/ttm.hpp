@@ -72,6 +72,12 @@ struct StridedArgs {
     // mode are loaded by tiles that run at nearly the same time.
     int64_t plane;
     int nplane, pgroup;
+    // Persistent last pass: xsweep != 0 gives the workgroups of XCD x (block
+    // index mod 8) the contiguous tile range [x per, (x + 1) per), per =
+    // ceil(ntiles / 8), walked by its blocks in steps of their count, so that
+    // the tiles of one XCD sweep one block of planes and the regulariser's
+    // neighbour loads find the neighbouring tiles in that XCD's L2.
+    int xsweep;
     // flattened-column pass (strided_flat_tile): division by trail
     uint32_t tmul;
     int tshift;
@@ -734,6 +740,57 @@ __device__ __forceinline__ void pipe_store(const PipeRegs& r, bf16* Xs, float* P
     }
 }
 
+// Middle-mode regulariser taps of a thread's IPT items (the band rows of R_k,
+// k = 2 .. N-1): rmid[i] += R_k taps of P around the item's E columns, modes in
+// ascending order and, per mode, the centre first and then the offsets -2, -1,
+// +1, +2 (out-of-range offsets read the centre against a zero coefficient).
+// Item i of a thread is row j = threadIdx.x / GPR + i * (CTA_WG / GPR) at the
+// column c = (threadIdx.x % GPR) * E of every item, so the mode index, its band
+// row and the neighbour offsets are formed once per mode.  Rows past J - 1 read
+// row J - 1 and are not used.  P is addressed with 32-bit byte offsets from its
+// base (the launcher checks that P spans less than 4 GiB).
+template <int IPT, int GPR, int E, int LDP, int H>
+__device__ __forceinline__ void mid_taps(const StencilArgs<float>& st, const float* Pw, int J, int trail,
+                                         int t0, floatx4 (&rmid)[IPT]) {
+    typedef floatx4 vt;
+    const char* __restrict__ Pb = reinterpret_cast<const char*>(st.P);
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));   // rows and offsets are re-formed per tile, not held in registers
+    const int c = (tid % GPR) * E;
+    const int t = t0 + c;
+    const int N = st.order;
+    for (int k = 1; k < N - 1; ++k) {
+        const float* __restrict__ rb = st.rband[k];
+        if (!rb) continue;
+        const int sk = (int)st.stride[k], nk = (int)st.ext[k];
+        const int u = fast_div(t, st.smul[k], st.sshift[k]);
+        const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
+        const float* br = rb + ik * 5;
+        const float b0 = br[0], b1 = br[1], b2 = br[2], b3 = br[3], b4 = br[4];
+        uint32_t off[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
+            const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
+            off[q] = (uint32_t)(dd * sk) * 4u;
+        }
+#pragma unroll 2
+        for (int i = 0; i < IPT; ++i) {
+            const int j = min(tid / GPR + i * (CTA_WG / GPR), J - 1);
+            const vt pc = *reinterpret_cast<const vt*>(Pw + j * LDP + H + c);
+            const uint32_t base = (uint32_t)(j * trail + t) * 4u;
+            vt nbv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) nbv[q] = *reinterpret_cast<const vt*>(Pb + (base + off[q]));
+            rmid[i] += b2 * pc;
+            rmid[i] += b0 * nbv[0];
+            rmid[i] += b1 * nbv[1];
+            rmid[i] += b3 * nbv[2];
+            rmid[i] += b4 * nbv[3];
+        }
+    }
+}
+
 // Persistent, pipelined last pass (see PipeRegs); K <= 128, kpad == 128.
 __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned char* smem,
                                                  const StencilArgs<float>& st, double& dot_acc,
@@ -744,12 +801,12 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
     constexpr int KPAD = 128;
     constexpr int TN = PIPE_TN, H = PIPE_H, LDP = PIPE_LDP;
     constexpr int E = 4, LDQ = TN + E, VEC = T::VEC;
-    constexpr int ldx = KPAD + 8;
     constexpr int JT = 2, CT = 2;
     const int K = a.K;
     const int trail = (int)a.trail;
     const int N = st.order;
     const int nN = (int)st.ext[N - 1];
+    constexpr int ldx = KPAD + 8;
     constexpr size_t a_bytes = ((size_t)(TN * ldx * 2) > (size_t)(KPAD * LDQ * 4) ? (size_t)(TN * ldx * 2)
                                                                                     : (size_t)(KPAD * LDQ * 4));
     bf16* Xs = reinterpret_cast<bf16*>(smem);
@@ -801,34 +858,7 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
         for (int i = 0; i < IPT; ++i)
 #pragma unroll
             for (int e = 0; e < E; ++e) rmid[i][e] = Tv(0);
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            // items past the last row read row J-1 and are not used
-            const int it = min(threadIdx.x + i * CTA_WG, nitem - 1);
-            const int j = it / GPR;
-            const int c = (it - j * GPR) * E;
-            const int t = t0 + c;
-            const vt pc = *reinterpret_cast<const vt*>(Pw + j * LDP + H + c);
-            const Tv* __restrict__ pb = P + (int64_t)j * trail + t;
-            for (int k = 1; k < N - 1; ++k) {
-                const Tv* __restrict__ rb = st.rband[k];
-                if (!rb) continue;
-                const int sk = (int)st.stride[k], nk = (int)st.ext[k];
-                const int u = fast_div(t, st.smul[k], st.sshift[k]);
-                const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
-                const Tv* br = rb + ik * 5;
-                vt nbv[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
-                    const int dd = (ik + d >= 0 && ik + d < nk) ? d : 0;
-                    nbv[q] = *reinterpret_cast<const vt*>(pb + dd * sk);
-                }
-                rmid[i] += br[2] * pc;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) rmid[i] += br[q < 2 ? q : q + 1] * nbv[q];
-            }
-        }
+        mid_taps<IPT, GPR, E, LDP, H>(st, Pw, a.J, trail, t0, rmid);
         // ---- MFMA (as normal_last_tile with JT = 2, WJ = 4, CT = 2) ----
         {
             const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -907,47 +937,57 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
 }
 
 // ---------------------------------------------------------------------------
-// Variant 6 of the pipelined last pass: the same tiles, prefetch and MFMA as
-// normal_last_pipe, with a column-affine epilogue.  Thread (cg, rg) = (tid % 8,
-// tid / 8) owns the 4 columns 4 cg .. 4 cg + 3 of the tile and the 4 rows
-// 4 rg .. 4 rg + 3.  The mode indices of its columns, the band rows of the
-// middle modes and of mode N, and the gather offsets are formed once per tile
-// (they do not depend on the row), the mode-1 taps of its 4 rows come from one
-// window of 8 LDS rows, and the middle-mode gathers of row j + 1 are those of
-// row j one mode-1 stride further.  Every element's sums are the same as
-// normal_last_pipe's, in the same order (identical Q).
+// Variant 6 of the pipelined last pass: normal_last_pipe's tiles, item layout,
+// prefetch and MFMA, with fewer LDS and vector instructions per item:
+//  * the P window has two zero rows above and below (rows -2, -1, K, K + 1),
+//    so the mode-1 taps need no clamping (their band coefficients are zero
+//    there anyway);
+//  * the band rows of mode 1 are staged 8 floats apart and those of mode N
+//    contiguously, so an item reads its 5 mode-1 and 4 x 5 mode-N
+//    coefficients as 16-byte vectors (2 + 5 reads instead of 25).
+// Every element's sums are the same as normal_last_pipe's, in the same order
+// (identical Q).
 __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned char* smem,
                                                   const StencilArgs<float>& st, double& dot_acc,
-                                                  int64_t first, int64_t step) {
+                                                  int64_t first, int64_t step, int64_t end) {
     typedef MT<bf16> T;
     typedef float Tv;
     typedef floatx4 vt;
     constexpr int KPAD = 128;
     constexpr int TN = PIPE_TN, H = PIPE_H, LDP = PIPE_LDP;
     constexpr int E = 4, LDQ = TN + E;
-    constexpr int ldx = KPAD + 8;
     constexpr int JT = 2, CT = 2;
-    constexpr int RPT = 4;                       // rows per thread
     const int K = a.K;
     const int trail = (int)a.trail;
     const int N = st.order;
     const int nN = (int)st.ext[N - 1];
+    constexpr int ldx = KPAD + 8;
     constexpr size_t a_bytes = ((size_t)(TN * ldx * 2) > (size_t)(KPAD * LDQ * 4) ? (size_t)(TN * ldx * 2)
                                                                                     : (size_t)(KPAD * LDQ * 4));
     bf16* Xs = reinterpret_cast<bf16*>(smem);
     float* Qs = reinterpret_cast<float*>(smem);
-    float* Pw = reinterpret_cast<float*>(smem + (a_bytes + 15) / 16 * 16);
-    float* band1 = Pw + (size_t)KPAD * LDP;
-    float* bandN = band1 + (size_t)KPAD * 5;
+    float* Pw0 = reinterpret_cast<float*>(smem + (a_bytes + 15) / 16 * 16);  // KPAD + 4 rows
+    float* Pw = Pw0 + 2 * LDP;                                                // row j at Pw + j * LDP
+    float* band1 = Pw0 + (size_t)(KPAD + 4) * LDP;                            // [j][8]
+    float* bandN = band1 + (size_t)KPAD * 8;                                  // [i][5]
     const bool has1 = st.rband[0] != nullptr;
     const bool hasN = st.rband[N - 1] != nullptr;
     float* __restrict__ Q = reinterpret_cast<float*>(a.Y);
     const float* __restrict__ P = st.P;
     const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
     if (has1)
-        for (int u = threadIdx.x; u < K * 5; u += CTA_WG) band1[u] = st.rband[0][u];
+        for (int u = threadIdx.x; u < K * 8; u += CTA_WG) {
+            const int jj = u >> 3, d = u & 7;
+            band1[u] = d < 5 ? st.rband[0][jj * 5 + d] : 0.f;
+        }
     if (hasN)
         for (int u = threadIdx.x; u < nN * 5; u += CTA_WG) bandN[u] = st.rband[N - 1][u];
+    // zero rows around the window: -2, -1 and K, K + 1 (never written by the tiles)
+    for (int u = threadIdx.x; u < 4 * LDP; u += CTA_WG) {
+        const int rr = u / LDP, cc = u - rr * LDP;
+        const int row = rr < 2 ? rr - 2 : K + rr - 2;
+        Pw[row * LDP + cc] = 0.f;
+    }
     const int cpp = (int)(a.plane / TN), per = cpp * a.pgroup;
     const float inv_per = a.pgroup > 0 ? 1.0f / (float)per : 0.f;
     const float inv_pg = a.pgroup > 0 ? 1.0f / (float)a.pgroup : 0.f;
@@ -958,52 +998,23 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
         const int c = small_div(rr, a.pgroup, inv_pg), ig = rr - c * a.pgroup;
         return (grp * a.pgroup + ig) * (int)a.plane + c * TN;
     };
-    const int cg = threadIdx.x & 7, rg = threadIdx.x >> 3;
-    const int c = cg * E;
-    const int j0 = rg * RPT;
     PipeRegs r;
-    if (first < a.ntiles) pipe_load<KPAD>(a, P, tcol(first), K, r);
+    if (first < end) pipe_load<KPAD>(a, P, tcol(first), K, r);
     const Tv lam = (Tv)st.lam;
-    for (int64_t tile = first; tile < a.ntiles; tile += step) {
+    constexpr int GPR = TN / E;
+    constexpr int IPT = KPAD * GPR / CTA_WG;
+    const int nitem = a.J * GPR;
+    for (int64_t tile = first; tile < end; tile += step) {
         const int t0 = tcol(tile);
-        const int t = t0 + c;
         pipe_store<KPAD>(r, Xs, Pw, K);
         __syncthreads();
-        // ---- middle-mode regulariser taps (rows past J read row J-1, unused) ----
-        vt rmid[RPT];
+        // ---- middle-mode regulariser taps (summed first, as every variant) ----
+        vt rmid[IPT];
 #pragma unroll
-        for (int w = 0; w < RPT; ++w)
+        for (int i = 0; i < IPT; ++i)
 #pragma unroll
-            for (int e = 0; e < E; ++e) rmid[w][e] = Tv(0);
-        for (int k = 1; k < N - 1; ++k) {
-            const Tv* __restrict__ rb = st.rband[k];
-            if (!rb) continue;
-            const int sk = (int)st.stride[k], nk = (int)st.ext[k];
-            const int u = fast_div(t, st.smul[k], st.sshift[k]);
-            const int ik = u - fast_div(u, st.emul[k], st.eshift[k]) * nk;
-            const Tv* br = rb + ik * 5;
-            const Tv b0 = br[0], b1 = br[1], b2 = br[2], b3 = br[3], b4 = br[4];
-            int off[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int d = q < 2 ? q - 2 : q - 1;  // -2, -1, 1, 2
-                off[q] = ((ik + d >= 0 && ik + d < nk) ? d : 0) * sk;
-            }
-#pragma unroll
-            for (int w = 0; w < RPT; ++w) {
-                const int j = min(j0 + w, a.J - 1);
-                const vt pc = *reinterpret_cast<const vt*>(Pw + j * LDP + H + c);
-                const Tv* __restrict__ pb = P + (int64_t)j * trail + t;
-                vt nbv[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) nbv[q] = *reinterpret_cast<const vt*>(pb + off[q]);
-                rmid[w] += b2 * pc;
-                rmid[w] += b0 * nbv[0];
-                rmid[w] += b1 * nbv[1];
-                rmid[w] += b3 * nbv[2];
-                rmid[w] += b4 * nbv[3];
-            }
-        }
+            for (int e = 0; e < E; ++e) rmid[i][e] = Tv(0);
+        mid_taps<IPT, GPR, E, LDP, H>(st, Pw, a.J, trail, t0, rmid);
         // ---- MFMA (as normal_last_pipe) ----
         {
             const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1015,7 +1026,7 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
 #pragma unroll
                 for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
             mfma_cols<bf16, JT, CT>(Xs, ldx, M, a.ldm, 0, jb, KPAD, acc);
-            if (tile + step < a.ntiles) pipe_load<KPAD>(a, P, tcol(tile + step), K, r);
+            if (tile + step < end) pipe_load<KPAD>(a, P, tcol(tile + step), K, r);
             __syncthreads();  // Xs is dead; its space becomes Qs
 #pragma unroll
             for (int x = 0; x < JT; ++x) {
@@ -1032,64 +1043,55 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
         }
         __syncthreads();
         // ---- epilogue: modes 1 and N from the LDS window ----
-        if (j0 < a.J) {
-            // mode-1 taps: a rolling window of 5 rows (clamped; out-of-range taps
-            // have zero band coefficients)
-            auto prow_at = [&](int jj) -> vt {
-                jj = min(max(jj, 0), K - 1);
-                return *reinterpret_cast<const vt*>(Pw + jj * LDP + H + c);
-            };
-            vt wm2 = prow_at(j0 - 2), wm1 = prow_at(j0 - 1), w0 = prow_at(j0), w1 = prow_at(j0 + 1);
-            // mode-N band rows of the 4 columns: 20 consecutive floats (i0 % 4 == 0)
-            const int i0 = hasN ? t - fast_div(t, st.emul[N - 1], st.eshift[N - 1]) * nN : 0;
-#pragma unroll
-            for (int w = 0; w < RPT; ++w) {
-                const int j = j0 + w;
-                if (j >= a.J) break;
-                const vt w2 = prow_at(j + 2);
-                const vt pc = w0;
-                vt s = *reinterpret_cast<const vt*>(Qs + j * LDQ + c);  // chain part, lam applied below
-                vt reg = rmid[w];
-                if (has1) {
-                    const Tv* b1 = band1 + j * 5;
-                    reg += b1[0] * wm2;
-                    reg += b1[1] * wm1;
-                    reg += b1[2] * w0;
-                    reg += b1[3] * w1;
-                    reg += b1[4] * w2;
-                }
-                if (hasN) {
-                    Tv bN[E * 5];
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) {
-                        const vt v = *reinterpret_cast<const vt*>(bandN + i0 * 5 + 4 * q);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) bN[4 * q + e] = v[e];
-                    }
-                    Tv wv[3 * E];
-                    const Tv* prow = Pw + j * LDP + H + c;
-                    const vt pl = *reinterpret_cast<const vt*>(prow - E);
-                    const vt pr = *reinterpret_cast<const vt*>(prow + E);
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        wv[e] = pl[e];
-                        wv[E + e] = pc[e];
-                        wv[2 * E + e] = pr[e];
-                    }
-#pragma unroll
-                    for (int e = 0; e < E; ++e)
-#pragma unroll
-                        for (int d = -2; d <= 2; ++d) reg[e] += bN[e * 5 + d + 2] * wv[E + e + d];
-                }
-                const vt qv = s + lam * reg;
-                *reinterpret_cast<vt*>(Q + (int64_t)j * trail + t) = qv;
-#pragma unroll
-                for (int e = 0; e < E; ++e) dot_acc += (double)pc[e] * (double)qv[e];
-                wm2 = wm1;
-                wm1 = w0;
-                w0 = w1;
-                w1 = w2;
+#pragma unroll 1
+        for (int i = 0; i < IPT; ++i) {
+            const int it = threadIdx.x + i * CTA_WG;
+            if (it >= nitem) break;
+            const int j = it / GPR;
+            const int c = (it - j * GPR) * E;
+            const int t = t0 + c;
+            const Tv* prow = Pw + j * LDP + H + c;  // prow[0] is P[j][t]
+            const int64_t base = (int64_t)j * trail + t;
+            const vt pc = *reinterpret_cast<const vt*>(prow);
+            vt s = *reinterpret_cast<const vt*>(Qs + j * LDQ + c);  // chain part, lam applied below
+            vt reg = rmid[i];
+            if (has1) {
+                const vt bl = *reinterpret_cast<const vt*>(band1 + j * 8);
+                const Tv b4 = band1[j * 8 + 4];
+                reg += bl[0] * *reinterpret_cast<const vt*>(prow - 2 * LDP);
+                reg += bl[1] * *reinterpret_cast<const vt*>(prow - LDP);
+                reg += bl[2] * pc;
+                reg += bl[3] * *reinterpret_cast<const vt*>(prow + LDP);
+                reg += b4 * *reinterpret_cast<const vt*>(prow + 2 * LDP);
             }
+            if (hasN) {
+                Tv w[3 * E];
+                const vt pl = *reinterpret_cast<const vt*>(prow - E);
+                const vt pr = *reinterpret_cast<const vt*>(prow + E);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    w[e] = pl[e];
+                    w[E + e] = pc[e];
+                    w[2 * E + e] = pr[e];
+                }
+                const int i0 = t - fast_div(t, st.emul[N - 1], st.eshift[N - 1]) * nN;
+                // the 4 x 5 coefficients are 20 consecutive floats (i0 % 4 == 0):
+                // coefficient x = 5 e + d + 2 multiplies tap d of column e, and
+                // each column's taps are taken in increasing d
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    const vt v = *reinterpret_cast<const vt*>(bandN + i0 * 5 + 4 * q);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int x = 4 * q + m, e = x / 5, d = x - 5 * e - 2;
+                        reg[e] += v[m] * w[E + e + d];
+                    }
+                }
+            }
+            const vt qv = s + lam * reg;
+            *reinterpret_cast<vt*>(Q + base) = qv;
+#pragma unroll
+            for (int e = 0; e < E; ++e) dot_acc += (double)pc[e] * (double)qv[e];
         }
         __syncthreads();  // LDS is reused by the next tile
     }
