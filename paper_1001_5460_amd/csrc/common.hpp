@@ -157,6 +157,21 @@ __device__ __forceinline__ double block_sum(double v, double* red /* >= 4 double
     return s;
 }
 
+// The same for workgroups of NW = 4 or 8 waves (red >= NW doubles in LDS).
+template <int NW>
+__device__ __forceinline__ double block_sum_w(double v, double* red) {
+    static_assert(NW == 4 || NW == 8, "4 or 8 waves");
+    v = wave_sum(v);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    double s = (red[0] + red[1]) + (red[2] + red[3]);
+    if constexpr (NW == 8) s += (red[4] + red[5]) + (red[6] + red[7]);
+    __syncthreads();
+    return s;
+}
+
 template <typename T> __device__ __forceinline__ bool is_finite_val(T x) {
     return __builtin_isfinite((double)x);
 }

@@ -131,6 +131,10 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
     bf16* Ms = reinterpret_cast<bf16*>(smem);                 // [128][SPIPE_LD]
     bf16* Xs = Ms + 128 * SPIPE_LD;                            // [64][SPIPE_XLD], swizzled
     const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
+    // the first tile's loads are issued before the factor's, so both latencies overlap
+    const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
+    bf16x8 r[4];
+    if (first < a.ntiles) spipe_load(a, first, r);
     // the factor, zero outside J x K
     for (int u = threadIdx.x; u < 128 * 16; u += CTA_WG) {
         const int j = u >> 4, c8 = (u & 15) * 8;
@@ -140,9 +144,6 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
         if (j < a.J && c8 < a.kpad) v = *reinterpret_cast<const bf16x8*>(M + (int64_t)j * a.ldm + c8);
         *reinterpret_cast<bf16x8*>(Ms + j * SPIPE_LD + c8) = v;
     }
-    const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
-    bf16x8 r[4];
-    if (first < a.ntiles) spipe_load(a, first, r);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int jb = wave * JT * 16;
@@ -361,31 +362,57 @@ __global__ __launch_bounds__(CTA_WG) __attribute__((amdgpu_waves_per_eu(3))) voi
 // Variant 6: the pipelined pass with fewer LDS and vector instructions per
 // item (normal_last_pipe6); LDS: 4 more window rows and 3 more floats per
 // mode-1 band row.
-__global__ __launch_bounds__(CTA_WG) __attribute__((amdgpu_waves_per_eu(3))) void k_normal_last_pipe6(
-    StridedArgs a, StencilArgs<float> st, const int* done) {
-    if (done && *done) return;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[4];
-    double dot = 0.0;
-    int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x, end = a.ntiles;
+// Tile range of a persistent last-pass workgroup (see StridedArgs::xsweep).
+__device__ __forceinline__ void last_tile_range(const StridedArgs& a, int64_t& first, int64_t& step,
+                                                int64_t& end) {
+    first = xcd_logical_block(blockIdx.x, gridDim.x);
+    step = gridDim.x;
+    end = a.ntiles;
     if (a.xsweep) {
         const int64_t per = (a.ntiles + CTA_XCDS - 1) / CTA_XCDS, x = blockIdx.x % CTA_XCDS;
         step = gridDim.x / CTA_XCDS;
         first = x * per + blockIdx.x / CTA_XCDS;
         end = min((x + 1) * per, a.ntiles);
     }
-    normal_last_pipe6(a, smem, st, dot, first, step, end);
+}
+
+__global__ __launch_bounds__(CTA_WG) __attribute__((amdgpu_waves_per_eu(3))) void k_normal_last_pipe6(
+    StridedArgs a, StencilArgs<float> st, const int* done) {
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[4];
+    double dot = 0.0;
+    int64_t first, step, end;
+    last_tile_range(a, first, step, end);
+    normal_last_pipe6<CTA_WG>(a, smem, st, dot, first, step, end);
     block_partial(dot, st.partials, red);
 }
 
+// Variant 7: variant 6 with 512 threads (8 waves) per workgroup, two
+// workgroups per CU.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_normal_last_pipe7(
+    StridedArgs a, StencilArgs<float> st, const int* done) {
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[8];
+    double dot = 0.0;
+    int64_t first, step, end;
+    last_tile_range(a, first, step, end);
+    normal_last_pipe6<512>(a, smem, st, dot, first, step, end);
+    const double s = block_sum_w<8>(dot, red);
+    if (threadIdx.x == 0) st.partials[blockIdx.x] = s;
+}
+
+// variant: 5 (k_normal_last_pipe), 6 (k_normal_last_pipe6) or 7 (k_normal_last_pipe7)
 static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int* grid_out, const int* done,
-                               hipStream_t s, bool colaff = false) {
+                               hipStream_t s, int variant) {
     const int N = st.order;
     const int nN = (int)st.ext[N - 1];
     if (a.kpad != 128 || a.K != a.J || a.trail % PIPE_TN != 0 || nN % 4 != 0 ||
         a.trail / PIPE_TN >= (int64_t(1) << 22) ||   // tile columns from float reciprocals
         (uint64_t)a.K * (uint64_t)a.trail * sizeof(float) >= (uint64_t(1) << 32))   // 32-bit offsets into P
         return hipErrorNotSupported;
+    const bool colaff = variant >= 6;
     a.ntt = a.trail / PIPE_TN;
     a.ntiles = a.ntt;
     a.pgroup = 0;
@@ -394,19 +421,28 @@ static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int*
     if (plane > 0 && plane % PIPE_TN == 0 && nplane % 8 == 0 && plane * nplane == a.trail) {
         a.plane = plane;
         a.nplane = nplane;
-        a.pgroup = 8;
+        // variants 6 and 7 walk groups of 16 planes inside per-XCD tile ranges
+        a.pgroup = colaff && nplane % 16 == 0 ? 16 : 8;
     }
-    a.xsweep = 0;
+    a.xsweep = colaff ? 1 : 0;
     const size_t xq = std::max<size_t>((size_t)PIPE_TN * (128 + 8) * 2, (size_t)128 * (PIPE_TN + 4) * 4);
     const size_t lds = colaff ? (xq + 15) / 16 * 16 + (size_t)(128 + 4) * PIPE_LDP * 4 + (size_t)128 * 8 * 4 +
                                     (size_t)nN * 5 * 4
                               : (xq + 15) / 16 * 16 + (size_t)128 * PIPE_LDP * 4 + (size_t)(128 + nN) * 5 * 4;
     if (lds > 64 * 1024) return hipErrorNotSupported;
-    // persistent grid: three workgroups per CU, a multiple of the XCD count
-    int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);
+    // persistent grid: three workgroups of 256 threads (two of 512) per CU, a
+    // multiple of the XCD count
+    const int per_cu = variant == 7 ? 2 : 3;
+    int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * per_cu);
     grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
     *grid_out = grid;
-    if (colaff) {
+    if (variant == 7) {
+        hipError_t e = ensure_lds(k_normal_last_pipe7, lds);
+        if (e != hipSuccess) return e;
+        k_normal_last_pipe7<<<grid, 512, lds, s>>>(a, st, done);
+        return hipGetLastError();
+    }
+    if (variant == 6) {
         hipError_t e = ensure_lds(k_normal_last_pipe6, lds);
         if (e != hipSuccess) return e;
         k_normal_last_pipe6<<<grid, CTA_WG, lds, s>>>(a, st, done);
@@ -517,11 +553,11 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
         }
         variant = 2;
     }
-    // variants 5 and 6: persistent and pipelined (BF16 chains, 96 < K <= 128);
-    // 6 with the column-affine epilogue
-    if (variant == 5 || variant == 6) {
+    // variants 5, 6 and 7: persistent and pipelined (BF16 chains, 96 < K <= 128);
+    // 6 and 7 with vector band reads and per-XCD tile ranges, 7 with 512 threads
+    if (variant >= 5 && variant <= 7) {
         if constexpr (sizeof(Tvec) == 4 && sizeof(Tc) == 2) {
-            const hipError_t e = go_last_pipe(a, st, grid, done, s, variant == 6);
+            const hipError_t e = go_last_pipe(a, st, grid, done, s, variant);
             if (e != hipErrorNotSupported) return e;
         }
         variant = 2;
@@ -572,6 +608,9 @@ __global__ __launch_bounds__(CTA_WG) void k_last_nr_pipe(StridedArgs a, const fl
     bf16* Ms = reinterpret_cast<bf16*>(smem);
     bf16* Xs = Ms + 128 * SPIPE_LD;
     const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
+    const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
+    bf16x8 r[4];
+    if (first < a.ntiles) spipe_load(a, first, r);   // in flight while the factor is staged
     for (int u = threadIdx.x; u < 128 * 16; u += CTA_WG) {
         const int j = u >> 4, c8 = (u & 15) * 8;
         bf16x8 v;
@@ -580,9 +619,6 @@ __global__ __launch_bounds__(CTA_WG) void k_last_nr_pipe(StridedArgs a, const fl
         if (j < a.J && c8 < a.kpad) v = *reinterpret_cast<const bf16x8*>(M + (int64_t)j * a.ldm + c8);
         *reinterpret_cast<bf16x8*>(Ms + j * SPIPE_LD + c8) = v;
     }
-    const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
-    bf16x8 r[4];
-    if (first < a.ntiles) spipe_load(a, first, r);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int jb = wave * JT * 16;
@@ -797,17 +833,6 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
     bf16* Ys = Zt + a.nbg * gm.zsz;
     const bf16* __restrict__ M1 = reinterpret_cast<const bf16*>(a.M1);
     const bf16* __restrict__ M2 = reinterpret_cast<const bf16*>(a.M2);
-    // factors into LDS (rows past the padded extents are never read)
-    for (int u = threadIdx.x; u < gm.nj1t * 16 * (a.k1pad / 8); u += CTA_WG) {
-        const int j = u / (a.k1pad / 8), c8 = (u - j * (a.k1pad / 8)) * 8;
-        *reinterpret_cast<bf16x8*>(M1s + j * gm.ld1 + c8) =
-            *reinterpret_cast<const bf16x8*>(M1 + (int64_t)j * a.ldm1 + c8);
-    }
-    for (int u = threadIdx.x; u < gm.nj2t * 16 * 4; u += CTA_WG) {
-        const int j = u >> 2, c8 = (u & 3) * 8;
-        *reinterpret_cast<bf16x8*>(M2s + j * gm.ld2 + c8) =
-            *reinterpret_cast<const bf16x8*>(M2 + (int64_t)j * a.ldm2 + c8);
-    }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int64_t bin = (int64_t)a.K1 * a.K2;
@@ -843,7 +868,18 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
             }
         }
     };
-    if (first < ngroups) fetch(first);
+    if (first < ngroups) fetch(first);   // in flight while the factors are staged
+    // factors into LDS (rows past the padded extents are never read)
+    for (int u = threadIdx.x; u < gm.nj1t * 16 * (a.k1pad / 8); u += CTA_WG) {
+        const int j = u / (a.k1pad / 8), c8 = (u - j * (a.k1pad / 8)) * 8;
+        *reinterpret_cast<bf16x8*>(M1s + j * gm.ld1 + c8) =
+            *reinterpret_cast<const bf16x8*>(M1 + (int64_t)j * a.ldm1 + c8);
+    }
+    for (int u = threadIdx.x; u < gm.nj2t * 16 * 4; u += CTA_WG) {
+        const int j = u >> 2, c8 = (u & 3) * 8;
+        *reinterpret_cast<bf16x8*>(M2s + j * gm.ld2 + c8) =
+            *reinterpret_cast<const bf16x8*>(M2 + (int64_t)j * a.ldm2 + c8);
+    }
     __syncthreads();  // factors staged
     for (int64_t grp = first; grp < ngroups; grp += step) {
         const int64_t blk0 = grp * a.nbg;

@@ -676,22 +676,25 @@ inline size_t normal_last_lds(int kpad, int K, int J, int nN) {
 // after them, so they are in flight while the current tile computes.  The
 // band coefficients are staged once per workgroup.  Same sums in the same
 // order as normal_last_tile (identical Q).
-struct PipeRegs {
-    bf16x8 x[2];        // rows 2 kp, 2 kp + 1 of the X tile, 8 columns
-    floatx4 p[5];       // P window chunks owned by this thread (K <= 128 rows x 10 chunks)
+template <int NT>
+struct PipeRegsT {
+    bf16x8 x[2];                     // rows 2 kp, 2 kp + 1 of the X tile, 8 columns (threads < 256)
+    floatx4 p[(1280 + NT - 1) / NT]; // P window chunks owned by this thread (K <= 128 rows x 10 chunks)
 };
+typedef PipeRegsT<CTA_WG> PipeRegs;
 
 constexpr int PIPE_TN = 32;
 constexpr int PIPE_H = 4;
 constexpr int PIPE_LDP = PIPE_TN + 2 * PIPE_H;   // 40 floats: 10 chunks of 4 per row
 
-template <int KPAD>
+template <int KPAD, int NT = CTA_WG>
 __device__ __forceinline__ void pipe_load(const StridedArgs& a, const float* __restrict__ P, int t0, int K,
-                                          PipeRegs& r) {
+                                          PipeRegsT<NT>& r) {
     const bf16* __restrict__ X = reinterpret_cast<const bf16*>(a.X);
     const int trail = (int)a.trail;
-    // X: unit = (row pair kp, column group cg of 8), cg fastest so that 4 lanes read a row's 64 bytes
-    {
+    // X: unit = (row pair kp, column group cg of 8), cg fastest so that 4 lanes read a row's 64 bytes;
+    // the first 256 threads own the 256 units
+    if (NT == 256 || threadIdx.x < 256) {
         const int cg = threadIdx.x & 3, kp = threadIdx.x >> 2;  // kp < 64 covers K <= 128
         const int t = t0 + cg * 8;
 #pragma unroll
@@ -704,10 +707,10 @@ __device__ __forceinline__ void pipe_load(const StridedArgs& a, const float* __r
             r.x[h] = v;
         }
     }
-    // P window: K rows x 10 chunks of 4 floats, chunk u = threadIdx.x + 256 i
+    // P window: K rows x 10 chunks of 4 floats, chunk u = threadIdx.x + NT i
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        const int u = threadIdx.x + CTA_WG * i;
+    for (int i = 0; i < (1280 + NT - 1) / NT; ++i) {
+        const int u = threadIdx.x + NT * i;
         const int row = u / 10, ch = u - row * 10;
         const int t = t0 - PIPE_H + ch * 4;
         floatx4 v = {0.f, 0.f, 0.f, 0.f};
@@ -716,10 +719,10 @@ __device__ __forceinline__ void pipe_load(const StridedArgs& a, const float* __r
     }
 }
 
-template <int KPAD>
-__device__ __forceinline__ void pipe_store(const PipeRegs& r, bf16* Xs, float* Pw, int K) {
+template <int KPAD, int NT = CTA_WG>
+__device__ __forceinline__ void pipe_store(const PipeRegsT<NT>& r, bf16* Xs, float* Pw, int K) {
     constexpr int ldx = KPAD + 8;
-    {
+    if (NT == 256 || threadIdx.x < 256) {
         const int cg = threadIdx.x & 3, kp = threadIdx.x >> 2;
         if (2 * kp < KPAD) {
 #pragma unroll
@@ -733,8 +736,8 @@ __device__ __forceinline__ void pipe_store(const PipeRegs& r, bf16* Xs, float* P
         }
     }
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        const int u = threadIdx.x + CTA_WG * i;
+    for (int i = 0; i < (1280 + NT - 1) / NT; ++i) {
+        const int u = threadIdx.x + NT * i;
         const int row = u / 10, ch = u - row * 10;
         if (row < K) *reinterpret_cast<floatx4*>(Pw + row * PIPE_LDP + ch * 4) = r.p[i];
     }
@@ -744,12 +747,12 @@ __device__ __forceinline__ void pipe_store(const PipeRegs& r, bf16* Xs, float* P
 // k = 2 .. N-1): rmid[i] += R_k taps of P around the item's E columns, modes in
 // ascending order and, per mode, the centre first and then the offsets -2, -1,
 // +1, +2 (out-of-range offsets read the centre against a zero coefficient).
-// Item i of a thread is row j = threadIdx.x / GPR + i * (CTA_WG / GPR) at the
+// Item i of a thread is row j = threadIdx.x / GPR + i * (NT / GPR) at the
 // column c = (threadIdx.x % GPR) * E of every item, so the mode index, its band
 // row and the neighbour offsets are formed once per mode.  Rows past J - 1 read
 // row J - 1 and are not used.  P is addressed with 32-bit byte offsets from its
 // base (the launcher checks that P spans less than 4 GiB).
-template <int IPT, int GPR, int E, int LDP, int H>
+template <int IPT, int GPR, int E, int LDP, int H, int NT = CTA_WG>
 __device__ __forceinline__ void mid_taps(const StencilArgs<float>& st, const float* Pw, int J, int trail,
                                          int t0, floatx4 (&rmid)[IPT]) {
     typedef floatx4 vt;
@@ -775,8 +778,8 @@ __device__ __forceinline__ void mid_taps(const StencilArgs<float>& st, const flo
             off[q] = (uint32_t)(dd * sk) * 4u;
         }
 #pragma unroll 2
-        for (int i = 0; i < IPT; ++i) {
-            const int j = min(tid / GPR + i * (CTA_WG / GPR), J - 1);
+        for (int i = 0; i < IPT; ++i) {   // at most two items' gathers in flight
+            const int j = min(tid / GPR + i * (NT / GPR), J - 1);
             const vt pc = *reinterpret_cast<const vt*>(Pw + j * LDP + H + c);
             const uint32_t base = (uint32_t)(j * trail + t) * 4u;
             vt nbv[4];
@@ -819,10 +822,6 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
     float* __restrict__ Q = reinterpret_cast<float*>(a.Y);
     const float* __restrict__ P = st.P;
     const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
-    if (has1)
-        for (int u = threadIdx.x; u < K * 5; u += CTA_WG) band1[u] = st.rband[0][u];
-    if (hasN)
-        for (int u = threadIdx.x; u < nN * 5; u += CTA_WG) bandN[u] = st.rband[N - 1][u];
     // first column of a tile (last_tile_col) with 32-bit quotients from float
     // reciprocals: the tile count is below 2^22 (checked by the launcher)
     const int cpp = (int)(a.plane / TN), per = cpp * a.pgroup;
@@ -837,6 +836,10 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
     };
     PipeRegs r;
     if (first < a.ntiles) pipe_load<KPAD>(a, P, tcol(first), K, r);
+    if (has1)
+        for (int u = threadIdx.x; u < K * 5; u += CTA_WG) band1[u] = st.rband[0][u];
+    if (hasN)
+        for (int u = threadIdx.x; u < nN * 5; u += CTA_WG) bandN[u] = st.rband[N - 1][u];
     const Tv lam = (Tv)st.lam;
     // Order of the memory traffic inside one tile.  The vector-memory counter
     // retires loads in issue order, so a load waits for every load issued
@@ -946,7 +949,10 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
 //    contiguously, so an item reads its 5 mode-1 and 4 x 5 mode-N
 //    coefficients as 16-byte vectors (2 + 5 reads instead of 25).
 // Every element's sums are the same as normal_last_pipe's, in the same order
-// (identical Q).
+// (identical Q).  NT = 256 (4 waves, 4 items per thread) is variant 6;
+// NT = 512 (8 waves of 16 output rows, 2 items per thread, so that a thread's
+// gathers of one mode are all in flight together) is variant 7.
+template <int NT>
 __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned char* smem,
                                                   const StencilArgs<float>& st, double& dot_acc,
                                                   int64_t first, int64_t step, int64_t end) {
@@ -956,7 +962,7 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
     constexpr int KPAD = 128;
     constexpr int TN = PIPE_TN, H = PIPE_H, LDP = PIPE_LDP;
     constexpr int E = 4, LDQ = TN + E;
-    constexpr int JT = 2, CT = 2;
+    constexpr int JT = 8 * 64 / NT, CT = 2;   // a wave owns 16 JT output rows
     const int K = a.K;
     const int trail = (int)a.trail;
     const int N = st.order;
@@ -975,19 +981,6 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
     float* __restrict__ Q = reinterpret_cast<float*>(a.Y);
     const float* __restrict__ P = st.P;
     const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
-    if (has1)
-        for (int u = threadIdx.x; u < K * 8; u += CTA_WG) {
-            const int jj = u >> 3, d = u & 7;
-            band1[u] = d < 5 ? st.rband[0][jj * 5 + d] : 0.f;
-        }
-    if (hasN)
-        for (int u = threadIdx.x; u < nN * 5; u += CTA_WG) bandN[u] = st.rband[N - 1][u];
-    // zero rows around the window: -2, -1 and K, K + 1 (never written by the tiles)
-    for (int u = threadIdx.x; u < 4 * LDP; u += CTA_WG) {
-        const int rr = u / LDP, cc = u - rr * LDP;
-        const int row = rr < 2 ? rr - 2 : K + rr - 2;
-        Pw[row * LDP + cc] = 0.f;
-    }
     const int cpp = (int)(a.plane / TN), per = cpp * a.pgroup;
     const float inv_per = a.pgroup > 0 ? 1.0f / (float)per : 0.f;
     const float inv_pg = a.pgroup > 0 ? 1.0f / (float)a.pgroup : 0.f;
@@ -998,15 +991,28 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
         const int c = small_div(rr, a.pgroup, inv_pg), ig = rr - c * a.pgroup;
         return (grp * a.pgroup + ig) * (int)a.plane + c * TN;
     };
-    PipeRegs r;
-    if (first < end) pipe_load<KPAD>(a, P, tcol(first), K, r);
+    PipeRegsT<NT> r;
+    if (first < end) pipe_load<KPAD, NT>(a, P, tcol(first), K, r);   // in flight while the bands are staged
+    if (has1)
+        for (int u = threadIdx.x; u < K * 8; u += NT) {
+            const int jj = u >> 3, d = u & 7;
+            band1[u] = d < 5 ? st.rband[0][jj * 5 + d] : 0.f;
+        }
+    if (hasN)
+        for (int u = threadIdx.x; u < nN * 5; u += NT) bandN[u] = st.rband[N - 1][u];
+    // zero rows around the window: -2, -1 and K, K + 1 (never written by the tiles)
+    for (int u = threadIdx.x; u < 4 * LDP; u += NT) {
+        const int rr = u / LDP, cc = u - rr * LDP;
+        const int row = rr < 2 ? rr - 2 : K + rr - 2;
+        Pw[row * LDP + cc] = 0.f;
+    }
     const Tv lam = (Tv)st.lam;
     constexpr int GPR = TN / E;
-    constexpr int IPT = KPAD * GPR / CTA_WG;
+    constexpr int IPT = KPAD * GPR / NT;
     const int nitem = a.J * GPR;
     for (int64_t tile = first; tile < end; tile += step) {
         const int t0 = tcol(tile);
-        pipe_store<KPAD>(r, Xs, Pw, K);
+        pipe_store<KPAD, NT>(r, Xs, Pw, K);
         __syncthreads();
         // ---- middle-mode regulariser taps (summed first, as every variant) ----
         vt rmid[IPT];
@@ -1014,7 +1020,7 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
         for (int i = 0; i < IPT; ++i)
 #pragma unroll
             for (int e = 0; e < E; ++e) rmid[i][e] = Tv(0);
-        mid_taps<IPT, GPR, E, LDP, H>(st, Pw, a.J, trail, t0, rmid);
+        mid_taps<IPT, GPR, E, LDP, H, NT>(st, Pw, a.J, trail, t0, rmid);
         // ---- MFMA (as normal_last_pipe) ----
         {
             const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1026,7 +1032,7 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
 #pragma unroll
                 for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
             mfma_cols<bf16, JT, CT>(Xs, ldx, M, a.ldm, 0, jb, KPAD, acc);
-            if (tile + step < end) pipe_load<KPAD>(a, P, tcol(tile + step), K, r);
+            if (tile + step < end) pipe_load<KPAD, NT>(a, P, tcol(tile + step), K, r);
             __syncthreads();  // Xs is dead; its space becomes Qs
 #pragma unroll
             for (int x = 0; x < JT; ++x) {
@@ -1045,7 +1051,7 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
         // ---- epilogue: modes 1 and N from the LDS window ----
 #pragma unroll 1
         for (int i = 0; i < IPT; ++i) {
-            const int it = threadIdx.x + i * CTA_WG;
+            const int it = threadIdx.x + i * NT;
             if (it >= nitem) break;
             const int j = it / GPR;
             const int c = (it - j * GPR) * E;

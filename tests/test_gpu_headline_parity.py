@@ -38,7 +38,8 @@ pytestmark = pytest.mark.gpu
 N = (128, 128, 96, 24)
 M = (192, 192, 144, 36)
 PIPE = (2, 2, 5)      # persistent tail, middle and last passes
-PIPE6 = (2, 2, 6)     # the same with the column-affine last-pass epilogue
+PIPE6 = (2, 2, 6)     # the same with vector band reads and per-XCD tile ranges
+PIPE7 = (2, 2, 7)     # the same with 512-thread workgroups in the last pass
 PLAIN = (0, 0, 0)     # one tile per workgroup
 U_BF16 = 2.0 ** -8
 
@@ -90,7 +91,7 @@ def test_integer_apply_bit_exact_at_full_size():
     assert op.band_width > 4          # random columns: the dense passes run
     Pd = dev(P, torch.float32)
     dot = torch.zeros(1, dtype=torch.float64, device="cuda")
-    for variants in (PIPE, PIPE6, PLAIN):
+    for variants in (PIPE, PIPE6, PIPE7, PLAIN):
         cta.cta_op_set_tuning(op.handle, "bf16", *variants)
         Q = op.apply(Pd, chain="bf16", dot=dot)
         torch.cuda.synchronize()
@@ -115,7 +116,7 @@ def test_random_apply_elementwise_bound_at_full_size():
     bound = 8.5 * U_BF16 * chain_abs + 1e-6 * reg_abs + 1e-30
 
     op = cta.Operator(p.A, p.D, p.lam)
-    for variants in (PIPE, PIPE6):
+    for variants in (PIPE, PIPE6, PIPE7):
         cta.cta_op_set_tuning(op.handle, "bf16", *variants)
         Q = op.apply(Pd, chain="bf16")
         torch.cuda.synchronize()
@@ -139,13 +140,13 @@ def test_persistent_cg_passes_match_plain_at_full_size(precond):
         op.set_preconditioner(181 * p.lam)
     B = dev(np.random.default_rng(44).standard_normal(N), torch.float32)
     out = []
-    for variants in (PLAIN, PIPE, PIPE6):
+    for variants in (PLAIN, PIPE, PIPE6, PIPE7):
         cta.cta_op_set_tuning(op.handle, "bf16", *variants)
         X, info = op.solve(B, precision="bf16", rtol=1e-30, max_iter=6, check_every=6,
                            precond=precond)
         assert info["iters"] == 6, info
         out.append(X.clone())
-    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+    assert all(torch.equal(out[0], o) for o in out[1:])
     if precond:
         R = dev(np.random.default_rng(45).standard_normal(N), torch.float32)
         Z = []
