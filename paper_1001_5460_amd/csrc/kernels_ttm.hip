@@ -70,6 +70,8 @@ static hipError_t go_strided(StridedArgs a, const int* done, hipStream_t s) {
 constexpr int SPIPE_TN = 64;
 constexpr int SPIPE_LD = 128 + 8;   // LDS pitch (bf16) of the factor rows
 constexpr int SPIPE_XLD = 128;      // LDS pitch (bf16) of the X columns
+constexpr int SPIPE_YLD = 64 + 8;   // LDS pitch (bf16) of the output rows (over the X tile)
+constexpr int SPIPE_XYS = 128 * SPIPE_YLD > SPIPE_TN * SPIPE_XLD ? 128 * SPIPE_YLD : SPIPE_TN * SPIPE_XLD;
 
 // An X tile sits in LDS as [64 columns t][128 K values] (zero past K), with the
 // sixteen 16-byte chunks of column t permuted by XOR with xs_swz(t).  A wave's
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
     constexpr int JT = 2, CT = 4, VEC = T::VEC;
     extern __shared__ __align__(16) unsigned char smem[];
     bf16* Ms = reinterpret_cast<bf16*>(smem);                 // [128][SPIPE_LD]
-    bf16* Xs = Ms + 128 * SPIPE_LD;                            // [64][SPIPE_XLD], swizzled
+    bf16* Xs = Ms + 128 * SPIPE_LD;                            // [64][SPIPE_XLD], swizzled; SPIPE_XYS
     const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
     // the first tile's loads are issued before the factor's, so both latencies overlap
     const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
@@ -174,18 +176,27 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
         const int b = fast_div((int)tile, a.tmul, a.tshift);
         const int64_t t0 = (tile - (int64_t)b * a.ntt) * SPIPE_TN;
         bf16* yb = Y + (int64_t)b * a.J * a.trail + t0;
+        // the output tile goes through LDS (over the X tile) so that every row's
+        // 128 bytes leave as whole 16-byte pieces, 8 lanes to a row
+        __syncthreads();  // every wave has read its X fragments
+        bf16* Ys = Xs;    // [128][SPIPE_YLD]
 #pragma unroll
         for (int x = 0; x < JT; ++x) {
             const int j = jb + x * 16 + l16;
-            if (j >= a.J) continue;
 #pragma unroll
             for (int y = 0; y < CT; ++y) {
                 typedef bf16 __attribute__((ext_vector_type(4))) bf16x4;
                 bf16x4 o;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) o[q] = (bf16)acc[x][y][q];
-                *reinterpret_cast<bf16x4*>(yb + (int64_t)j * a.trail + y * 16 + 4 * g) = o;
+                *reinterpret_cast<bf16x4*>(Ys + j * SPIPE_YLD + y * 16 + 4 * g) = o;
             }
+        }
+        __syncthreads();
+        for (int u = threadIdx.x; u < a.J * 8; u += CTA_WG) {
+            const int j = u >> 3, c8 = (u & 7) * 8;
+            *reinterpret_cast<bf16x8*>(yb + (int64_t)j * a.trail + c8) =
+                *reinterpret_cast<const bf16x8*>(Ys + j * SPIPE_YLD + c8);
         }
         __syncthreads();  // Xs is rewritten by the next tile
     }
@@ -197,7 +208,7 @@ static hipError_t go_strided_pipe(StridedArgs a, const int* done, hipStream_t s)
     a.ntiles = a.lead * a.ntt;
     if (a.ntiles >= ((int64_t)1 << 30)) return hipErrorNotSupported;
     fastdiv_init((uint32_t)a.ntt, &a.tmul, &a.tshift);
-    const size_t lds = ((size_t)128 * SPIPE_LD + (size_t)SPIPE_TN * SPIPE_XLD) * sizeof(bf16);
+    const size_t lds = ((size_t)128 * SPIPE_LD + (size_t)SPIPE_XYS) * sizeof(bf16);
     hipError_t e = ensure_lds(k_strided_pipe, lds);
     if (e != hipSuccess) return e;
     int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);
