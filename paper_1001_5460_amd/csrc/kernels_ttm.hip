@@ -1,6 +1,7 @@
 // gfx950 kernels and launchers of the mode-product passes and of the
 // normal-operator pass (see ttm.hpp for the tiling).
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "launch.hpp"
@@ -798,9 +799,12 @@ static hipError_t tail_T(const TailArgs& a, size_t lds, hipStream_t s) {
 // Persistent, pipelined fused tail pass (BF16 chain, x and p updates fused):
 // M1 and M2 are staged in LDS once per workgroup, and the r, p (and x)
 // fragments of the workgroup's next group of blocks are loaded into registers
-// right after the current group's have been consumed, so they arrive while
+// right after the current group's new values are stored, so they arrive while
 // the second MFMA step and the write-back run (which touch only LDS and
-// store).  Same sums, in the same order, as tail_group.  Shapes: k1pad and
+// store).  Every lane loads every slot, at a clamped address where the slot is
+// unused, so that no register keeps an old value across the load and nothing
+// waits for the loads before the next group.  Same sums, in the same order,
+// as tail_group.  Shapes: k1pad and
 // J1 <= 128, K2 <= 32 with K2 % 8 == 0, J2 <= 32, at most TPIPE_TPW 16-row
 // tiles per wave per group.
 constexpr int TPIPE_TPW = 3;
@@ -860,22 +864,27 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
     const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
     const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
     f4 rr[TPIPE_TPW][2], pp[TPIPE_TPW][2], xx[TPIPE_TPW][2];
+    // Every lane loads every slot: slots past the group's tiles, rows past K1 and
+    // columns past K2 read a clamped (valid, unused) address instead of
+    // skipping the load, so no register has to keep its old value and the
+    // loads stay in flight until step 1 of the next group uses them.
+    const float* __restrict__ Xsrc = Xg ? Xg : R;
     auto fetch = [&](int64_t grp) {
         const int64_t blk0 = grp * a.nbg;
         const int nb = (int)std::min<int64_t>(a.nbg, a.nblk - blk0);
 #pragma unroll
         for (int i = 0; i < TPIPE_TPW; ++i) {
-            const int it = wave + CTA_WAVES * i;
-            if (it >= nb * gm.ni1t) continue;
+            int it = wave + CTA_WAVES * i;
+            if (it >= nb * gm.ni1t) it = 0;
             const int bl = it / gm.ni1t, ti = it - bl * gm.ni1t;
-            const int i1 = ti * 16 + l16;
-            if (i1 >= a.K1 || k2 >= a.K2) continue;
-            const int64_t off = (blk0 + bl) * bin + (int64_t)i1 * a.K2 + k2;
+            const int i1 = min(ti * 16 + l16, a.K1 - 1);
+            const int kc = min(k2, a.K2 - VEC);
+            const int64_t off = (blk0 + bl) * bin + (int64_t)i1 * a.K2 + kc;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 rr[i][h] = *reinterpret_cast<const f4*>(R + off + 4 * h);
                 pp[i][h] = *reinterpret_cast<const f4*>(Pg + off + 4 * h);
-                if (Xg) xx[i][h] = *reinterpret_cast<const f4*>(Xg + off + 4 * h);
+                if constexpr (!FR) xx[i][h] = *reinterpret_cast<const f4*>(Xsrc + off + 4 * h);
             }
         }
     };
@@ -896,6 +905,9 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
         const int64_t blk0 = grp * a.nbg;
         const int nb = (int)std::min<int64_t>(a.nbg, a.nblk - blk0);
         // ---- step 1 from the fetched fragments: x += alpha p, p = r + beta p, Zt ----
+        // All new values are formed before the first store: a wait for fetched
+        // data issued after a store also waits for that store.
+        f4 nv[TPIPE_TPW][2], nx[TPIPE_TPW][2];   // new p (FR: new r) and new x
 #pragma unroll
         for (int i = 0; i < TPIPE_TPW; ++i) {
             const int it = wave + CTA_WAVES * i;
@@ -904,23 +916,20 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
             const int i1 = ti * 16 + l16;
             typename T::frag xf = T::zfrag();
             if (i1 < a.K1 && k2 < a.K2) {
-                const int64_t off = (blk0 + bl) * bin + (int64_t)i1 * a.K2 + k2;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     if constexpr (FR) {
-                        const f4 rn = rr[i][h] - alpha * pp[i][h];
-                        *reinterpret_cast<f4*>(Rw + off + 4 * h) = rn;
+                        nv[i][h] = rr[i][h] - alpha * pp[i][h];
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            xf[4 * h + v] = (bf16)rn[v];
-                            dot += (double)rn[v] * (double)rn[v];
+                            xf[4 * h + v] = (bf16)nv[i][h][v];
+                            dot += (double)nv[i][h][v] * (double)nv[i][h][v];
                         }
                     } else {
-                        if (Xg) *reinterpret_cast<f4*>(Xg + off + 4 * h) = xx[i][h] + alpha * pp[i][h];
-                        const f4 pn = rr[i][h] + beta * pp[i][h];
-                        *reinterpret_cast<f4*>(Pg + off + 4 * h) = pn;
+                        if (Xg) nx[i][h] = xx[i][h] + alpha * pp[i][h];
+                        nv[i][h] = rr[i][h] + beta * pp[i][h];
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) xf[4 * h + v] = (bf16)pn[v];
+                        for (int v = 0; v < 4; ++v) xf[4 * h + v] = (bf16)nv[i][h][v];
                     }
                 }
             }
@@ -934,6 +943,25 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
                     const int j2 = x * 16 + l16;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) Zb[j2 * gm.ldz + ti * 16 + T::arow(lane, r)] = (bf16)acc[r];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TPIPE_TPW; ++i) {
+            const int it = wave + CTA_WAVES * i;
+            if (it >= nb * gm.ni1t) continue;
+            const int bl = it / gm.ni1t, ti = it - bl * gm.ni1t;
+            const int i1 = ti * 16 + l16;
+            if (i1 < a.K1 && k2 < a.K2) {
+                const int64_t off = (blk0 + bl) * bin + (int64_t)i1 * a.K2 + k2;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if constexpr (FR) {
+                        *reinterpret_cast<f4*>(Rw + off + 4 * h) = nv[i][h];
+                    } else {
+                        if (Xg) *reinterpret_cast<f4*>(Xg + off + 4 * h) = nx[i][h];
+                        *reinterpret_cast<f4*>(Pg + off + 4 * h) = nv[i][h];
+                    }
                 }
             }
         }
@@ -988,10 +1016,25 @@ static hipError_t go_tail_pipe(TailArgs a, hipStream_t s, int* grid_out = nullpt
     const size_t lds = tail_pipe_lds(gm, a.nbg);
     if (lds > 64 * 1024) return hipErrorNotSupported;
     const int64_t ngroups = (a.nblk + a.nbg - 1) / a.nbg;
-    int grid = (int)std::min<int64_t>(ngroups, (int64_t)device_cus() * 3);
-    grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
     hipError_t e = ensure_lds(k_tail_pipe<FR>, lds);
     if (e != hipSuccess) return e;
+    // persistent grid: as many workgroups per CU as are resident at once (at
+    // most 3; the x and p form holds enough registers for 2), a multiple of
+    // the XCD count
+    static std::atomic<int64_t> cached{-1};   // lds << 8 | workgroups per CU
+    int64_t c = cached.load(std::memory_order_relaxed);
+    int per_cu;
+    if (c >= 0 && (size_t)(c >> 8) == lds) {
+        per_cu = (int)(c & 255);
+    } else {
+        per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tail_pipe<FR>, CTA_WG, lds) != hipSuccess)
+            per_cu = 0;
+        per_cu = std::max(1, std::min(per_cu, 3));
+        cached.store((int64_t)lds << 8 | per_cu, std::memory_order_relaxed);
+    }
+    int grid = (int)std::min<int64_t>(ngroups, (int64_t)device_cus() * per_cu);
+    grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
     if (grid_out) *grid_out = grid;
     k_tail_pipe<FR><<<grid, CTA_WG, lds, s>>>(a);
     return hipGetLastError();
