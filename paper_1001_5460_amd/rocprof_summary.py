@@ -14,7 +14,8 @@ active dispatches, and derives
 * MFMA work from SQ_INSTS_VALU_MFMA_MOPS_BF16 (units of 512 flops per count) over the kernel's
   duration, as a fraction of the BF16 dense peak, and the MFMA-busy share
   SQ_VALU_MFMA_BUSY_CYCLES / (4 SIMDs x SQ_BUSY_CU_CYCLES);
-* DRAM read requests (TCC_EA0_RDREQ_DRAM, 64-byte requests), wave stall share
+* DRAM reads from TCC_EA0_RDREQ_DRAM, in bytes per request measured on the same copy kernel
+  (--calib-dram: bytes the copy reads / its requests), wave stall share
   SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES and LDS bank-conflict cycles per LDS instruction.
 
 A dispatch is active when its duration (or, without timestamps, its first counter) is at least a
@@ -112,6 +113,15 @@ def counters(args):
             kib, n, _ = _avg_active(per[copy[0]], ctr)
             calib[ctr] = kib
             scale[ctr] = (args.calib_bytes / 1024.0) / kib
+    dram_req = None
+    if args.calib_dram:
+        per = _per_kernel(args.calib_dram)
+        copy = [k for k in per if "k_cast<float, float>" in k]
+        if not copy:
+            raise SystemExit(f"no copy kernel in {args.calib_dram}")
+        req, n, _ = _avg_active(per[copy[0]], "TCC_EA0_RDREQ_DRAM")
+        dram_req = args.calib_bytes / req
+        calib["TCC_EA0_RDREQ_DRAM"] = req
     wanted = dict(s.split("=", 1) for s in args.kernels)
     summary = {}
     for bench_name, sub in wanted.items():
@@ -144,11 +154,11 @@ def counters(args):
             row["wait_share"] = row["SQ_WAIT_INST_ANY"] / row["SQ_WAVE_CYCLES"]
         if row.get("SQ_LDS_BANK_CONFLICT") is not None and row.get("SQ_INSTS_LDS"):
             row["lds_conflict_cycles_per_instr"] = row["SQ_LDS_BANK_CONFLICT"] / row["SQ_INSTS_LDS"]
-        if row.get("TCC_EA0_RDREQ_DRAM") is not None:
-            row["dram_read_bytes_per_launch"] = int(row["TCC_EA0_RDREQ_DRAM"] * 64)
+        if row.get("TCC_EA0_RDREQ_DRAM") is not None and dram_req:
+            row["dram_read_bytes_per_launch"] = int(row["TCC_EA0_RDREQ_DRAM"] * dram_req)
         summary[bench_name] = row
     js = {"workload": args.workload, "tuning": json.loads(args.tuning) if args.tuning else None,
-          "read_scale": scale["FETCH_SIZE"], "write_scale": scale["WRITE_SIZE"],
+          "read_scale": scale["FETCH_SIZE"], "write_scale": scale["WRITE_SIZE"], "dram_request_bytes": dram_req,
           "calibration_kib": calib, "source": args.out, "command": args.cmd,
           "sources": args.sources, "kernels": {}}
     for k, row in summary.items():
@@ -161,10 +171,11 @@ def counters(args):
              "```", args.cmd, "```", "",
              "Per kernel, averages over active dispatches (a tenth of the 90th-percentile duration or "
              "more). FETCH_SIZE counts what the L2 fetches from the fabric (Infinity Cache hits "
-             "included), so it bounds HBM reads from above; TCC_EA0_RDREQ_DRAM counts 64-byte DRAM read "
+             "included), so it bounds HBM reads from above; TCC_EA0_RDREQ_DRAM counts DRAM read "
              "requests. Copy calibration (the library's FP32 copy kernel, "
              f"{args.calib_bytes} bytes read and written per launch): "
-             f"FETCH x{scale['FETCH_SIZE']:.4f}, WRITE x{scale['WRITE_SIZE']:.4f}.", ""]
+             f"FETCH x{scale['FETCH_SIZE']:.4f}, WRITE x{scale['WRITE_SIZE']:.4f}"
+             + (f", {dram_req:.1f} bytes per DRAM read request." if dram_req else "."), ""]
     cols = [("avg_us", "avg us", "{:.1f}"), ("traffic_bytes_per_launch", "traffic MB", "{:.1f}"),
             ("dram_read_bytes_per_launch", "DRAM read MB", "{:.1f}"),
             ("mfma_bf16_tflops", "MFMA BF16 TFLOP/s", "{:.2f}"),
@@ -206,6 +217,7 @@ def main(argv=None):
     c.add_argument("--run", action="append", default=[], required=True)
     c.add_argument("--calib-fetch")
     c.add_argument("--calib-write")
+    c.add_argument("--calib-dram")
     c.add_argument("--calib-bytes", type=int, default=4 * 37748736)
     c.add_argument("--kernels", nargs="+", default=[])
     c.add_argument("--cmd", required=True)
