@@ -948,8 +948,10 @@ __device__ __forceinline__ void normal_last_pipe(const StridedArgs& a, unsigned 
 //  * the band rows of mode 1 are staged 8 floats apart and those of mode N
 //    contiguously, so an item reads its 5 mode-1 and 4 x 5 mode-N
 //    coefficients as 16-byte vectors (2 + 5 reads instead of 25).
-// Every element's sums are the same as normal_last_pipe's, in the same order
-// (identical Q).  NT = 256 (4 waves, 4 items per thread) is variant 6;
+// The G_1 fragments a wave multiplies with (its 16 JT rows, all K) are
+// loaded into registers once per workgroup instead of from the cache for
+// every tile.  Every element's sums are the same as normal_last_pipe's, in
+// the same order (identical Q).  NT = 256 (4 waves, 4 items per thread) is variant 6;
 // NT = 512 (8 waves of 16 output rows, 2 items per thread, so that a thread's
 // gathers of one mode are all in flight together) is variant 7.
 template <int NT>
@@ -1010,6 +1012,20 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
     constexpr int GPR = TN / E;
     constexpr int IPT = KPAD * GPR / NT;
     const int nitem = a.J * GPR;
+    // this wave's G_1 fragments (16 JT output rows, all KPAD columns) stay in
+    // registers for the workgroup's whole life
+    constexpr int NKS = KPAD / T::KSTEP;
+    typename T::frag mreg[JT][NKS];
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int jb = wave * JT * 16;
+#pragma unroll
+        for (int x = 0; x < JT; ++x)
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks)
+                mreg[x][ks] = *reinterpret_cast<const typename T::frag*>(
+                    M + (int64_t)(jb + x * 16 + (lane & 15)) * a.ldm + ks * T::KSTEP + T::VEC * (lane >> 4));
+    }
     for (int64_t tile = first; tile < end; tile += step) {
         const int t0 = tcol(tile);
         pipe_store<KPAD, NT>(r, Xs, Pw, K);
@@ -1031,7 +1047,18 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
             for (int x = 0; x < JT; ++x)
 #pragma unroll
                 for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
-            mfma_cols<bf16, JT, CT>(Xs, ldx, M, a.ldm, 0, jb, KPAD, acc);
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+                typename T::frag xa[CT];
+#pragma unroll
+                for (int y = 0; y < CT; ++y)
+                    xa[y] = *reinterpret_cast<const typename T::frag*>(Xs + (y * 16 + l16) * ldx + ks * T::KSTEP +
+                                                                        T::VEC * g);
+#pragma unroll
+                for (int x = 0; x < JT; ++x)
+#pragma unroll
+                    for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mreg[x][ks], acc[x][y]);
+            }
             if (tile + step < end) pipe_load<KPAD, NT>(a, P, tcol(tile + step), K, r);
             __syncthreads();  // Xs is dead; its space becomes Qs
 #pragma unroll
