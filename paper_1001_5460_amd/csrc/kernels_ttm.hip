@@ -64,9 +64,10 @@ static hipError_t go_strided(StridedArgs a, const int* done, hipStream_t s) {
 }
 
 // Persistent, pipelined strided pass (BF16, K, J <= 128, trail % 64 == 0):
-// the factor is staged in LDS once per workgroup, and the next 64-column X tile
-// is loaded into registers while the current one multiplies from LDS, so the
-// only vector-memory loads of a tile are its successor's.  Same sums, in the
+// each wave's factor fragments (its 32 output rows) are loaded into registers
+// once per workgroup, and the next 64-column X tile is loaded into registers
+// while the current one multiplies from LDS, so the only vector-memory loads
+// of a tile are its successor's.  Same sums, in the
 // same order, as strided_tile with JT = 2, WJ = 4, CT = 4.
 constexpr int SPIPE_TN = 64;
 constexpr int SPIPE_LD = 128 + 8;   // LDS pitch (bf16) of the factor rows
@@ -131,25 +132,30 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
     typedef MT<bf16> T;
     constexpr int JT = 2, CT = 4, VEC = T::VEC;
     extern __shared__ __align__(16) unsigned char smem[];
-    bf16* Ms = reinterpret_cast<bf16*>(smem);                 // [128][SPIPE_LD]
-    bf16* Xs = Ms + 128 * SPIPE_LD;                            // [64][SPIPE_XLD], swizzled; SPIPE_XYS
+    bf16* Xs = reinterpret_cast<bf16*>(smem);                  // [64][SPIPE_XLD], swizzled; SPIPE_XYS
     const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
-    // the first tile's loads are issued before the factor's, so both latencies overlap
     const int64_t first = xcd_logical_block(blockIdx.x, gridDim.x), step = gridDim.x;
     bf16x8 r[4];
     if (first < a.ntiles) spipe_load(a, first, r);
-    // the factor, zero outside J x K
-    for (int u = threadIdx.x; u < 128 * 16; u += CTA_WG) {
-        const int j = u >> 4, c8 = (u & 15) * 8;
-        bf16x8 v;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (bf16)0.f;
-        if (j < a.J && c8 < a.kpad) v = *reinterpret_cast<const bf16x8*>(M + (int64_t)j * a.ldm + c8);
-        *reinterpret_cast<bf16x8*>(Ms + j * SPIPE_LD + c8) = v;
-    }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int jb = wave * JT * 16;
+    // this wave's factor fragments (its 32 output rows, zero past J) stay in
+    // registers for the workgroup's whole life
+    constexpr int NKS = 128 / T::KSTEP;
+    const int nks = a.kpad / T::KSTEP;
+    typename T::frag mreg[JT][NKS];
+#pragma unroll
+    for (int x = 0; x < JT; ++x) {
+        const int j = jb + x * 16 + l16;
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            mreg[x][ks] = T::zfrag();
+            if (ks < nks && j < a.J)
+                mreg[x][ks] = *reinterpret_cast<const typename T::frag*>(M + (int64_t)j * a.ldm + ks * T::KSTEP +
+                                                                          VEC * g);
+        }
+    }
     bf16* __restrict__ Y = reinterpret_cast<bf16*>(a.Y);
     for (int64_t tile = first; tile < a.ntiles; tile += step) {
         xs_store(Xs, r);
@@ -160,19 +166,17 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
         for (int x = 0; x < JT; ++x)
 #pragma unroll
             for (int y = 0; y < CT; ++y) acc[x][y] = T::zero();
-        const int nks = a.kpad / T::KSTEP;
-        for (int ks = 0; ks < nks; ++ks) {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            if (ks >= nks) break;
             const int k0 = ks * T::KSTEP + VEC * g;
-            typename T::frag xa[CT], mb[JT];
+            typename T::frag xa[CT];
 #pragma unroll
             for (int y = 0; y < CT; ++y) xa[y] = xs_frag<typename T::frag>(Xs, y * 16 + l16, k0 >> 3);
 #pragma unroll
             for (int x = 0; x < JT; ++x)
-                mb[x] = *reinterpret_cast<const typename T::frag*>(Ms + (jb + x * 16 + l16) * SPIPE_LD + k0);
 #pragma unroll
-            for (int x = 0; x < JT; ++x)
-#pragma unroll
-                for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mb[x], acc[x][y]);
+                for (int y = 0; y < CT; ++y) acc[x][y] = T::mma(xa[y], mreg[x][ks], acc[x][y]);
         }
         const int b = fast_div((int)tile, a.tmul, a.tshift);
         const int64_t t0 = (tile - (int64_t)b * a.ntt) * SPIPE_TN;
@@ -209,10 +213,19 @@ static hipError_t go_strided_pipe(StridedArgs a, const int* done, hipStream_t s)
     a.ntiles = a.lead * a.ntt;
     if (a.ntiles >= ((int64_t)1 << 30)) return hipErrorNotSupported;
     fastdiv_init((uint32_t)a.ntt, &a.tmul, &a.tshift);
-    const size_t lds = ((size_t)128 * SPIPE_LD + (size_t)SPIPE_XYS) * sizeof(bf16);
+    const size_t lds = (size_t)SPIPE_XYS * sizeof(bf16);
     hipError_t e = ensure_lds(k_strided_pipe, lds);
     if (e != hipSuccess) return e;
-    int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * 3);
+    // persistent grid: the workgroups per CU that are resident at once
+    static std::atomic<int> cached{0};
+    int per_cu = cached.load(std::memory_order_relaxed);
+    if (per_cu <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_strided_pipe, CTA_WG, lds) != hipSuccess)
+            per_cu = 0;
+        per_cu = std::max(1, std::min(per_cu, 8));
+        cached.store(per_cu, std::memory_order_relaxed);
+    }
+    int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)device_cus() * per_cu);
     grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
     k_strided_pipe<<<grid, CTA_WG, lds, s>>>(a, done);
     return hipGetLastError();
