@@ -160,6 +160,67 @@ def cpu_baseline(p, X_gpu_host, iters=3, X_extra=None):
     return base, judge, judge_extra
 
 
+def run_small_configs(cta, torch, steps=3):
+    """Configs 0 (32^3, FP64 CG to 1e-10) and 1 (64^3 x 32, FP32 CG to 1e-6): RHS
+    chain from Y in HBM plus the solve, one warm-up and `steps` timed solves
+    each.  Returns the summary and the host copies of the solutions (for the
+    oracle's judge in the host-side leg)."""
+    import workload
+    dev = torch.device("cuda:0")
+    out, sols = {}, {}
+    for c, prec, dt in ((0, "f64", torch.float64), (1, "f32", torch.float32)):
+        p = workload.config_problem(c)
+        op = cta.Operator(p.A, p.D, p.lam)
+        chain = "f64" if prec == "f64" else "f32"
+        Xt = torch.from_numpy(p.X_true).to(dev)
+        Y = op.forward(Xt, chain="f64")
+        Y += torch.from_numpy(p.noise).to(dev)
+        Y = Y.to(dt)
+        B = torch.empty(p.n, dtype=dt, device=dev)
+        X = torch.empty(p.n, dtype=dt, device=dev)
+        op.tune(chain, reps=3)
+
+        def step():
+            op.rhs(Y, B, chain=chain)
+            _, info = op.solve(B, X, precision=prec, rtol=p.rtol, max_iter=20000, check_every=16)
+            return info
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / steps
+        info = infos[-1]
+        out[f"config{c}"] = {"shape": list(p.n), "precision": prec, "rtol": p.rtol,
+                             "time_s": round(dt_s, 5), "iters": info["iters"],
+                             "iters_per_s": round(info["iters"] / dt_s, 1),
+                             "status": info["status"], "rel_res_true": info["rel_res_true"],
+                             "steps": steps}
+        sols[c] = (p, X.double().cpu().numpy(), info["iters"])
+        op.close()
+    return out, sols
+
+
+def small_config_judge(sols):
+    """The oracle's FP64 residual judge of the config 0 and 1 solutions, and the
+    oracle's own CG iteration count for config 0 (host side, untimed)."""
+    import oracle
+    res = {}
+    for c, (p, X, gpu_iters) in sols.items():
+        op = oracle.NormalOperator(p.A, p.D, p.lam)
+        B = op.rhs(op.forward(p.X_true) + p.noise)
+        r = {"oracle_rel_residual": oracle.relative_residual(X, B, op), "rtol": p.rtol}
+        r["ok"] = r["oracle_rel_residual"] <= 1.01 * p.rtol
+        if c == 0:
+            ref = oracle.cg(op, B, rtol=p.rtol)
+            r["oracle_iters"] = ref.iters
+            r["gpu_iters"] = gpu_iters
+            r["iters_within_10pct"] = abs(gpu_iters - ref.iters) <= 0.1 * ref.iters + 1
+        res[f"config{c}"] = r
+    return res
+
+
 def run_batched(args, cta, torch):
     """256 independent 3-D problems (extents drawn from {24, 32, 48, 64, 96}, collocation
     1.5n x n, lambda 1e-3, FP32 CG to 1e-6) in one persistent launch, against the
@@ -457,6 +518,8 @@ def main():
     ap.add_argument("--sop-max-iter", type=int, default=5000)
     ap.add_argument("--ws-seeds", type=int, default=100,
                     help="held-out seeds (from 10000) of the warm-start gain measurement")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip configs 0 and 1 (time and iterations) in the headline line")
     ap.add_argument("--no-warmstart", action="store_true",
                     help="skip the warm-start summary in the headline line")
     ap.add_argument("--set-tuning", action="append", default=[],
@@ -840,6 +903,11 @@ def main():
         # the learned warm start on its own workload (held-out seeds), outside the timed region
         out["warm_start"] = run_warmstart(args, cta, torch, list(range(10000, 10000 + args.ws_seeds)))
 
+    small_sols = None
+    if not args.no_small:
+        # configs 0 and 1 (parity shapes), outside the timed region
+        out["small_configs"], small_sols = run_small_configs(cta, torch)
+
     if not args.no_cpu_baseline:
         extra = {name: x.cpu().numpy() for name, x in extra_solutions.items()}
         base, judge, jx = cpu_baseline(p, X_plain.cpu().numpy(), X_extra=extra)
@@ -849,6 +917,10 @@ def main():
         for name, r in jx.items():
             out["parity"][f"oracle_rel_residual_of_{name}_solution"] = r
             out["parity"]["ok"] = out["parity"]["ok"] and r <= 1e-8 * 1.01
+        if small_sols:
+            out["parity"]["small_configs"] = small_config_judge(small_sols)
+            out["parity"]["ok"] = out["parity"]["ok"] and all(
+                v["ok"] for v in out["parity"]["small_configs"].values())
     print(json.dumps(out), flush=True)
 
 
