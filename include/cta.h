@@ -186,14 +186,17 @@ cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void* stream);
  * shape) or 2 (persistent workgroups with the factor in LDS that load the next
  * 64-column tile while computing the current one, BF16 chains with
  * n_k <= 128 and the trailing extent a multiple of 64, else as 1), last
- * 0..7 (0, 1: tile shape; 2, 3: the narrow shape with its tiles walked
+ * 0..8 (0, 1: tile shape; 2, 3: the narrow shape with its tiles walked
  * along the second mode first, in groups of 8 planes or all planes; 4: row
  * blocks of 32 with the whole stencil staged on chip, F32/BF16 chains of
  * order 3 or 4, else as 2; 5: persistent workgroups that load the next
  * tile while computing the current one, BF16 chains with 96 < n_1 <= 128,
  * else as 2; 6: as 5 with zero rows around the LDS window, vector reads
  * of the band coefficients and each XCD's workgroups sweeping one range of
- * tiles; 7: as 6 with workgroups of 512 threads, two per CU). */
+ * tiles; 7: as 6 with workgroups of 512 threads, two per CU; 8: one
+ * 1024-thread workgroup per CU sweeping a run of tiles along one plane of
+ * the second mode with P in an on-chip ring, order 4 with n_N <= 24, else
+ * as 6). */
 cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* host_variants3);
 cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3);
 

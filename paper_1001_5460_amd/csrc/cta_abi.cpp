@@ -1029,11 +1029,12 @@ extern "C" cta_status cta_tune_op(cta_op op, cta_precision chain, int reps, void
     const bool use_band = op->use_band;
     op->use_band = false;
     // tail pass: 2 block counts; middle passes: 2 tile shapes and the
-    // persistent pipelined form; last pass: 8 (two tile shapes, two
+    // persistent pipelined form; last pass: 9 (two tile shapes, two
     // plane-grouped tile orders of the narrow one, row blocks with the whole
-    // stencil in LDS, and the persistent pipelined form with its two
-    // epilogues, the second also with 512-thread workgroups)
-    for (int combo = 0; combo < 48; ++combo) {
+    // stencil in LDS, the persistent pipelined form with its two epilogues,
+    // the second also with 512-thread workgroups, and plane sweeps with P in
+    // an LDS ring)
+    for (int combo = 0; combo < 54; ++combo) {
         op->var_tail[tc] = combo % 2;
         op->var_mid[tc] = (combo / 2) % 3;
         op->var_last[tc] = combo / 6;
@@ -1134,8 +1135,8 @@ extern "C" cta_status cta_op_get_tuning(cta_op op, cta_precision chain, int* hos
 extern "C" cta_status cta_op_set_tuning(cta_op op, cta_precision chain, const int* host_variants3) {
     if (!op || !host_variants3) return fail(CTA_ERR_ARG, "NULL argument");
     for (int i = 0; i < 3; ++i)
-        if (host_variants3[i] < 0 || host_variants3[i] > (i == 2 ? 7 : 2))
-            return fail(CTA_ERR_ARG, "variants must be 0..2 (tail, middle) and 0..7 (last)");
+        if (host_variants3[i] < 0 || host_variants3[i] > (i == 2 ? 8 : 2))
+            return fail(CTA_ERR_ARG, "variants must be 0..2 (tail, middle) and 0..8 (last)");
     const int tc = prec_tc(chain);
     op->var_tail[tc] = host_variants3[0];
     op->var_mid[tc] = host_variants3[1];

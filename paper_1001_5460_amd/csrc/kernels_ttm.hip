@@ -428,6 +428,54 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (threadIdx.x == 0) st.partials[blockIdx.x] = s;
 }
 
+// Variant 8 (normal_last_ring): one 1024-thread workgroup per CU.
+__global__ __launch_bounds__(RING_NT) __attribute__((amdgpu_waves_per_eu(4))) void k_normal_last_ring(
+    StridedArgs a, StencilArgs<float> st, RingGeom rg, const int* done) {
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[RING_NT / 64];
+    double dot = 0.0;
+    normal_last_ring(a, smem, st, rg, dot);
+    dot = wave_sum(dot);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < RING_NT / 64; ++w) s += red[w];
+        st.partials[blockIdx.x] = s;
+    }
+}
+
+// Variant 8 when the shape allows it (order 4, K = J <= 128, n_N % 4 == 0 and
+// n_N <= 24, planes of the second mode a multiple of 32 columns, P below 4 GiB);
+// hipErrorNotSupported otherwise.
+static hipError_t go_last_ring(StridedArgs a, const StencilArgs<float>& st, int* grid_out, const int* done,
+                               hipStream_t s) {
+    if (st.order != 4 || a.kpad != 128 || a.K != a.J || a.K < 1) return hipErrorNotSupported;
+    const int nN = (int)st.ext[3], n3 = (int)st.ext[2], n2 = (int)st.ext[1];
+    const int64_t plane = st.stride[1];
+    if (nN % 4 != 0 || nN > 24 || plane % RING_TN != 0 || plane < RING_TN || n2 * plane != a.trail ||
+        a.trail >= (int64_t(1) << 30) || (uint64_t)a.K * (uint64_t)a.trail * sizeof(float) >= (uint64_t(1) << 32))
+        return hipErrorNotSupported;
+    const size_t lds = ring_lds_bytes(a.K, n3, nN);
+    if (lds > 160 * 1024) return hipErrorNotSupported;
+    RingGeom rg;
+    rg.nplane = n2;
+    rg.plane = (int)plane;
+    rg.cpp = (int)(plane / RING_TN);
+    const int cus = device_cus();
+    rg.nseg = std::max(1, std::min(rg.cpp, (cus + n2 - 1) / n2));
+    rg.seg_len = (rg.cpp + rg.nseg - 1) / rg.nseg;
+    int grid = n2 * rg.nseg;
+    grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
+    hipError_t e = ensure_lds(k_normal_last_ring, lds);
+    if (e != hipSuccess) return e;
+    *grid_out = grid;
+    k_normal_last_ring<<<grid, RING_NT, lds, s>>>(a, st, rg, done);
+    return hipGetLastError();
+}
+
 // variant: 5 (k_normal_last_pipe), 6 (k_normal_last_pipe6) or 7 (k_normal_last_pipe7)
 static hipError_t go_last_pipe(StridedArgs a, const StencilArgs<float>& st, int* grid_out, const int* done,
                                hipStream_t s, int variant) {
@@ -579,7 +627,15 @@ static hipError_t last_T(StridedArgs a, const StencilDesc& d, double* partials, 
         variant = 2;
     }
     // variants 5, 6 and 7: persistent and pipelined (BF16 chains, 96 < K <= 128);
-    // 6 and 7 with vector band reads and per-XCD tile ranges, 7 with 512 threads
+    // 6 and 7 with vector band reads and per-XCD tile ranges, 7 with 512 threads;
+    // 8: one workgroup per CU sweeping a plane with P in an LDS ring
+    if (variant == 8) {
+        if constexpr (sizeof(Tvec) == 4 && sizeof(Tc) == 2) {
+            const hipError_t e = go_last_ring(a, st, grid, done, s);
+            if (e != hipErrorNotSupported) return e;
+        }
+        variant = 6;
+    }
     if (variant >= 5 && variant <= 7) {
         if constexpr (sizeof(Tvec) == 4 && sizeof(Tc) == 2) {
             const hipError_t e = go_last_pipe(a, st, grid, done, s, variant);

@@ -1131,6 +1131,306 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
 }
 
 // ---------------------------------------------------------------------------
+// Variant 8 of the pipelined last pass (tensor order 4, BF16 chain, K = J <=
+// 128, n_N <= 24, n_N % 4 == 0, the plane of the second mode a multiple of 32
+// columns).  One workgroup of 1024 threads per CU sweeps a run of
+// consecutive 32-column tiles of one plane of the second mode; the
+// workgroups of one XCD hold neighbouring planes, so the second mode's
+// neighbour planes are read by neighbouring workgroups at nearly the same
+// time and come from that XCD's L2.  P stays in LDS as a ring of 128 columns
+// (the tile and 48 columns either side) that slides by 32 columns per tile:
+// the third mode's taps (columns +- n_N, +- 2 n_N), the last mode's and the
+// first mode's come from LDS; only the second mode's four planes are
+// gathered.  A tile's 32 new ring columns and its X rows are loaded into
+// registers two tiles ahead, its gathers one tile ahead, and issued in the
+// order they are waited for.  One item (4 columns of one row) per thread.
+// Every element's sums are those of the other variants, in the same order
+// (identical Q).
+constexpr int RING_TN = 32;
+constexpr int RING_W = 128;          // ring columns (power of two)
+constexpr int RING_LD = RING_W + 8;  // pitch: rows 4 apart fall in disjoint halves of the banks
+constexpr int RING_NT = 1024;
+constexpr int RING_XLD = 128 + 8;    // X tile pitch (bf16)
+constexpr int RING_LDQ = RING_TN + 4;
+
+struct RingGeom {
+    int nplane, plane, nseg, cpp, seg_len;  // planes, plane width, segments per plane, chunks per plane
+};
+
+// LDS bytes of variant 8 (ring, X tile, Q tile, band rows of modes 1, 3, N)
+__host__ __device__ inline size_t ring_lds_bytes(int K, int n3, int nN) {
+    return (size_t)(K + 4) * RING_LD * 4 + (size_t)RING_TN * RING_XLD * 2 + (size_t)128 * RING_LDQ * 4 +
+           (size_t)128 * 8 * 4 + (size_t)n3 * 5 * 4 + (size_t)nN * 5 * 4;
+}
+
+struct RingRegs {
+    floatx4 p;   // 4 of the tile's 32 new ring columns, one row (row tid / 8)
+    bf16x8 x[2]; // rows 2 kp, 2 kp + 1 of the X tile, 8 columns (threads < 256)
+};
+
+// Row of a thread's item: within each wave's block of 8 rows, lanes 8q .. 8q+7
+// take row 4 (q mod 2) + q / 2, so one 16-lane LDS access reads rows 4 apart.
+__device__ __forceinline__ int ring_row(int tid) {
+    const int q = (tid >> 3) & 7;
+    return (tid >> 6) * 8 + (q & 1) * 4 + (q >> 1);
+}
+
+// A tile starting at column T reads the ring window [T - 48, T + 80); going
+// from the tile at T - 32 to it, the new columns are [T + 48, T + 80), which
+// take the ring slots of [T - 80, T - 48).  ring_get loads a thread's 4 of
+// those 32 columns of one row (row tid / 8) and, for threads < 256, two rows
+// of the tile's X rows; rows past K and columns outside the tensor read a
+// clamped address and are stored as zero by ring_put.
+__device__ __forceinline__ void ring_get_cols(const float* __restrict__ P, int trail, int T, int K, floatx4& v) {
+    const int row = threadIdx.x >> 3, ch = threadIdx.x & 7;
+    const int t = T + 48 + 4 * ch;
+    const bool ok = row < K && t >= 0 && t < trail;
+    v = *reinterpret_cast<const floatx4*>(P + (int64_t)(ok ? row : 0) * trail + (ok ? t : 0));
+}
+
+__device__ __forceinline__ void ring_put_cols(const floatx4& v, float* ring, int trail, int T, int K) {
+    const int row = threadIdx.x >> 3, ch = threadIdx.x & 7;
+    const int t = T + 48 + 4 * ch;
+    if (row < K) {
+        floatx4 w = v;
+        if (t < 0 || t >= trail) w = floatx4{0.f, 0.f, 0.f, 0.f};
+        *reinterpret_cast<floatx4*>(ring + (row + 2) * RING_LD + (t & (RING_W - 1))) = w;
+    }
+}
+
+__device__ __forceinline__ void ring_get_x(const StridedArgs& a, int T, int K, bf16x8 (&x)[2]) {
+    if (threadIdx.x < 256) {
+        const bf16* __restrict__ X = reinterpret_cast<const bf16*>(a.X);
+        const int cg = threadIdx.x & 3, kp = threadIdx.x >> 2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = min(2 * kp + h, K - 1);
+            x[h] = *reinterpret_cast<const bf16x8*>(X + (int64_t)k * a.trail + T + cg * 8);
+        }
+    }
+}
+
+__device__ __forceinline__ void ring_put_x(const bf16x8 (&x)[2], bf16* Xs, int K) {
+    if (threadIdx.x < 256) {
+        const int cg = threadIdx.x & 3, kp = threadIdx.x >> 2;
+        typedef bf16 __attribute__((ext_vector_type(2))) bf16x2;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            bf16x2 pr;
+            pr[0] = 2 * kp < K ? x[0][c] : (bf16)0.f;
+            pr[1] = 2 * kp + 1 < K ? x[1][c] : (bf16)0.f;
+            *reinterpret_cast<bf16x2*>(Xs + (cg * 8 + c) * RING_XLD + 2 * kp) = pr;
+        }
+    }
+}
+
+__device__ __forceinline__ void normal_last_ring(const StridedArgs& a, unsigned char* smem,
+                                                 const StencilArgs<float>& st, const RingGeom& rg,
+                                                 double& dot_acc) {
+    typedef MT<bf16> T;
+    typedef floatx4 vt;
+    constexpr int E = 4, NKS = 4;
+    const int K = a.K;
+    const int trail = (int)a.trail;
+    const int nN = (int)st.ext[3], n3 = (int)st.ext[2], n2 = (int)st.ext[1];
+    float* ring = reinterpret_cast<float*>(smem);                              // [K + 4][RING_LD]
+    bf16* Xs = reinterpret_cast<bf16*>(ring + (size_t)(K + 4) * RING_LD);      // [32][RING_XLD]
+    float* Qs = reinterpret_cast<float*>(Xs + (size_t)RING_TN * RING_XLD);     // [128][RING_LDQ]
+    float* band1 = Qs + (size_t)128 * RING_LDQ;                                // [j][8]
+    float* band3 = band1 + (size_t)128 * 8;                                    // [i3][5]
+    float* bandN = band3 + (size_t)n3 * 5;                                     // [i4][5]
+    const float* __restrict__ P = st.P;
+    float* __restrict__ Q = reinterpret_cast<float*>(a.Y);
+    const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
+    const bool has1 = st.rband[0] != nullptr, has2 = st.rband[1] != nullptr;
+    const bool has3 = st.rband[2] != nullptr, hasN = st.rband[3] != nullptr;
+    // this workgroup's plane and run of chunks (planes of one XCD side by side)
+    const int L = (int)xcd_logical_block(blockIdx.x, gridDim.x);
+    const int p = L / rg.nseg, seg = L - p * rg.nseg;
+    const int cbeg = seg * rg.seg_len, cend = min(rg.cpp, cbeg + rg.seg_len);
+    if (p >= rg.nplane || cbeg >= cend) return;   // uniform: the whole workgroup leaves
+    const int tbase = p * rg.plane;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, l16 = lane & 15;
+    // band rows and the ring's zero rows (-2, -1, K, K + 1)
+    if (has1)
+        for (int u = tid; u < K * 8; u += RING_NT) {
+            const int jj = u >> 3, d = u & 7;
+            band1[u] = d < 5 ? st.rband[0][jj * 5 + d] : 0.f;
+        }
+    if (has3)
+        for (int u = tid; u < n3 * 5; u += RING_NT) band3[u] = st.rband[2][u];
+    if (hasN)
+        for (int u = tid; u < nN * 5; u += RING_NT) bandN[u] = st.rband[3][u];
+    for (int u = tid; u < 4 * RING_LD; u += RING_NT) {
+        const int rr = u / RING_LD, cc = u - rr * RING_LD;
+        const int row = rr < 2 ? rr : K + rr;   // ring rows 0, 1 and K + 2, K + 3
+        ring[row * RING_LD + cc] = 0.f;
+    }
+    // the second mode's band row and in-range neighbour offsets: one plane per workgroup
+    float b2c[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    uint32_t off2[4] = {0u, 0u, 0u, 0u};
+    if (has2) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) b2c[q] = st.rband[1][p * 5 + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int d = q < 2 ? q - 2 : q - 1;
+            const int dd = (p + d >= 0 && p + d < n2) ? d : 0;
+            off2[q] = (uint32_t)(dd * rg.plane) * 4u;
+        }
+    }
+    // this wave's G_1 fragments (16 output rows, all K) for the whole sweep
+    const int rt = wave >> 1, ct = wave & 1;
+    typename T::frag mreg[NKS];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+        mreg[ks] = *reinterpret_cast<const typename T::frag*>(M + (int64_t)(rt * 16 + l16) * a.ldm +
+                                                              ks * T::KSTEP + T::VEC * g);
+    // the item: row j, columns c .. c + 3 of every tile
+    const int j = ring_row(tid);
+    const int c = (tid & 7) * E;
+    const bool jok = j < K;
+    const int jc = jok ? j : K - 1;
+    const char* __restrict__ Pb = reinterpret_cast<const char*>(P);
+    auto gather = [&](int t0, vt (&gv)[4]) {
+        const uint32_t base = (uint32_t)(jc * trail + t0 + c) * 4u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gv[q] = *reinterpret_cast<const vt*>(Pb + (base + off2[q]));
+    };
+    // prologue: the first tile's ring window [t0 - 48, t0 + 80) (the new
+    // columns of the tiles at t0 - 96, t0 - 64, t0 - 32 and t0) and X tile,
+    // the second tile's data, the first tile's gathers
+    const int t_first = tbase + cbeg * RING_TN;
+    {
+        floatx4 w[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) ring_get_cols(P, trail, t_first - 96 + 32 * b, K, w[b]);
+        bf16x8 x0[2];
+        ring_get_x(a, t_first, K, x0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) ring_put_cols(w[b], ring, trail, t_first - 96 + 32 * b, K);
+        ring_put_x(x0, Xs, K);
+    }
+    RingRegs rA, rB;   // the data of tile i + 1 is in rB before tile i for i - cbeg even, in rA for odd
+    vt gv[4];
+    gather(t_first, gv);
+    {
+        const int t1 = tbase + min(cbeg + 1, cend - 1) * RING_TN;
+        ring_get_cols(P, trail, t1, K, rB.p);
+        ring_get_x(a, t1, K, rB.x);
+    }
+    const float lam = (float)st.lam;
+    auto run_tile = [&](int ci, RingRegs& rnext, RingRegs& rfree) {
+        const int t0 = tbase + ci * RING_TN;
+        __syncthreads();   // ring window, X tile and bands of this tile are in LDS
+        const int t = t0 + c;
+        const int col = t & (RING_W - 1);
+        const float* rrow = ring + (jc + 2) * RING_LD;
+        const vt pc = *reinterpret_cast<const vt*>(rrow + col);
+        // ---- middle modes, second then third (as every variant) ----
+        vt rmid = vt{0.f, 0.f, 0.f, 0.f};
+        if (has2) {
+            rmid += b2c[2] * pc;
+            rmid += b2c[0] * gv[0];
+            rmid += b2c[1] * gv[1];
+            rmid += b2c[3] * gv[2];
+            rmid += b2c[4] * gv[3];
+        }
+        // the next tile's gathers, then the data of the tile after it
+        const int tn = tbase + min(ci + 1, cend - 1) * RING_TN;
+        gather(tn, gv);
+        {
+            const int t2 = tbase + min(ci + 2, cend - 1) * RING_TN;
+            ring_get_cols(P, trail, t2, K, rfree.p);
+            ring_get_x(a, t2, K, rfree.x);
+        }
+        if (has3) {
+            const int u = fast_div(t, st.smul[2], st.sshift[2]);
+            const int i3 = u - fast_div(u, st.emul[2], st.eshift[2]) * n3;
+            const float* br = band3 + i3 * 5;
+            vt nb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int d = q < 2 ? q - 2 : q - 1;
+                const int dd = (i3 + d >= 0 && i3 + d < n3) ? d : 0;
+                nb[q] = *reinterpret_cast<const vt*>(rrow + ((t + dd * nN) & (RING_W - 1)));
+            }
+            rmid += br[2] * pc;
+            rmid += br[0] * nb[0];
+            rmid += br[1] * nb[1];
+            rmid += br[3] * nb[2];
+            rmid += br[4] * nb[3];
+        }
+        // ---- MFMA: this wave's 16 x 16 block of the chain part ----
+        {
+            typename T::acc acc = T::zero();
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+                const typename T::frag xa = *reinterpret_cast<const typename T::frag*>(
+                    Xs + (ct * 16 + l16) * RING_XLD + ks * T::KSTEP + T::VEC * g);
+                acc = T::mma(xa, mreg[ks], acc);
+            }
+            const int jo = rt * 16 + l16;
+            vt o;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = acc[q];
+            *reinterpret_cast<vt*>(Qs + jo * RING_LDQ + ct * 16 + 4 * g) = o;
+        }
+        __syncthreads();   // Q tile complete
+        // ---- epilogue: modes 1 and N from the ring ----
+        if (jok) {
+            vt s = *reinterpret_cast<const vt*>(Qs + j * RING_LDQ + c);
+            vt reg = rmid;
+            if (has1) {
+                const vt bl = *reinterpret_cast<const vt*>(band1 + j * 8);
+                const float b4 = band1[j * 8 + 4];
+                reg += bl[0] * *reinterpret_cast<const vt*>(rrow - 2 * RING_LD + col);
+                reg += bl[1] * *reinterpret_cast<const vt*>(rrow - RING_LD + col);
+                reg += bl[2] * pc;
+                reg += bl[3] * *reinterpret_cast<const vt*>(rrow + RING_LD + col);
+                reg += b4 * *reinterpret_cast<const vt*>(rrow + 2 * RING_LD + col);
+            }
+            if (hasN) {
+                float w[3 * E];
+                const vt pl = *reinterpret_cast<const vt*>(rrow + ((t - E) & (RING_W - 1)));
+                const vt pr = *reinterpret_cast<const vt*>(rrow + ((t + E) & (RING_W - 1)));
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    w[e] = pl[e];
+                    w[E + e] = pc[e];
+                    w[2 * E + e] = pr[e];
+                }
+                const int i0 = t - fast_div(t, st.emul[3], st.eshift[3]) * nN;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    const vt v = *reinterpret_cast<const vt*>(bandN + i0 * 5 + 4 * q);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int x = 4 * q + m, e = x / 5, d = x - 5 * e - 2;
+                        reg[e] += v[m] * w[E + e + d];
+                    }
+                }
+            }
+            const vt qv = s + lam * reg;
+            *reinterpret_cast<vt*>(Q + (int64_t)j * trail + t) = qv;
+#pragma unroll
+            for (int e = 0; e < E; ++e) dot_acc += (double)pc[e] * (double)qv[e];
+        }
+        __syncthreads();   // the ring's oldest 32 columns, the X and Q tiles are free
+        if (ci + 1 < cend) {
+            ring_put_cols(rnext.p, ring, trail, tbase + (ci + 1) * RING_TN, K);
+            ring_put_x(rnext.x, Xs, K);
+        }
+    };
+    for (int ci = cbeg; ci < cend; ci += 2) {
+        run_tile(ci, rB, rA);
+        if (ci + 1 >= cend) break;
+        run_tile(ci + 1, rA, rB);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Last pass in row blocks (FP32 vectors, tensor order 3 or 4): a tile is 32
 // output rows x 32 columns, and everything the 17-point stencil reads is staged
 // in LDS with coalesced loads: P rows j0-2 .. j0+33 over the columns

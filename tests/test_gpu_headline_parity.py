@@ -40,6 +40,7 @@ M = (192, 192, 144, 36)
 PIPE = (2, 2, 5)      # persistent tail, middle and last passes
 PIPE6 = (2, 2, 6)     # the same with vector band reads and per-XCD tile ranges
 PIPE7 = (2, 2, 7)     # the same with 512-thread workgroups in the last pass
+PIPE8 = (2, 2, 8)     # the last pass sweeping planes with P in an LDS ring
 PLAIN = (0, 0, 0)     # one tile per workgroup
 U_BF16 = 2.0 ** -8
 
@@ -91,7 +92,7 @@ def test_integer_apply_bit_exact_at_full_size():
     assert op.band_width > 4          # random columns: the dense passes run
     Pd = dev(P, torch.float32)
     dot = torch.zeros(1, dtype=torch.float64, device="cuda")
-    for variants in (PIPE, PIPE6, PIPE7, PLAIN):
+    for variants in (PIPE, PIPE6, PIPE7, PIPE8, PLAIN):
         cta.cta_op_set_tuning(op.handle, "bf16", *variants)
         Q = op.apply(Pd, chain="bf16", dot=dot)
         torch.cuda.synchronize()
@@ -116,7 +117,7 @@ def test_random_apply_elementwise_bound_at_full_size():
     bound = 8.5 * U_BF16 * chain_abs + 1e-6 * reg_abs + 1e-30
 
     op = cta.Operator(p.A, p.D, p.lam)
-    for variants in (PIPE, PIPE6, PIPE7):
+    for variants in (PIPE, PIPE6, PIPE7, PIPE8):
         cta.cta_op_set_tuning(op.handle, "bf16", *variants)
         Q = op.apply(Pd, chain="bf16")
         torch.cuda.synchronize()
@@ -140,7 +141,7 @@ def test_persistent_cg_passes_match_plain_at_full_size(precond):
         op.set_preconditioner(181 * p.lam)
     B = dev(np.random.default_rng(44).standard_normal(N), torch.float32)
     out = []
-    for variants in (PLAIN, PIPE, PIPE6, PIPE7):
+    for variants in (PLAIN, PIPE, PIPE6, PIPE7, PIPE8):
         cta.cta_op_set_tuning(op.handle, "bf16", *variants)
         X, info = op.solve(B, precision="bf16", rtol=1e-30, max_iter=6, check_every=6,
                            precond=precond)

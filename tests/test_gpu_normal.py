@@ -119,7 +119,7 @@ def test_tile_variants_match_oracle(n, m, chain):
     P = dev(np.random.default_rng(11).standard_normal(n), dt)
     ref = ref_op(host(P))
     outs = []
-    for combo in range(72):   # tail 2 applies to the fused tail only; here it is tail 0
+    for combo in range(81):   # tail 2 applies to the fused tail only; here it is tail 0
         cta.cta_op_set_tuning(op.handle, chain, combo % 3, (combo // 3) % 3, combo // 9)
         Q = op.apply(P, chain=chain)
         torch.cuda.synchronize()
