@@ -1157,10 +1157,13 @@ struct RingGeom {
     int nplane, plane, nseg, cpp, seg_len;  // planes, plane width, segments per plane, chunks per plane
 };
 
+// band blocks start on 16-byte boundaries (the mode-N rows are read as float4)
+__host__ __device__ inline int ring_pad4(int n) { return (n + 3) & ~3; }
+
 // LDS bytes of variant 8 (ring, X tile, Q tile, band rows of modes 1, 3, N)
 __host__ __device__ inline size_t ring_lds_bytes(int K, int n3, int nN) {
     return (size_t)(K + 4) * RING_LD * 4 + (size_t)RING_TN * RING_XLD * 2 + (size_t)128 * RING_LDQ * 4 +
-           (size_t)128 * 8 * 4 + (size_t)n3 * 5 * 4 + (size_t)nN * 5 * 4;
+           (size_t)128 * 8 * 4 + (size_t)ring_pad4(n3 * 5) * 4 + (size_t)nN * 5 * 4;
 }
 
 struct RingRegs {
@@ -1238,15 +1241,17 @@ __device__ __forceinline__ void normal_last_ring(const StridedArgs& a, unsigned 
     float* Qs = reinterpret_cast<float*>(Xs + (size_t)RING_TN * RING_XLD);     // [128][RING_LDQ]
     float* band1 = Qs + (size_t)128 * RING_LDQ;                                // [j][8]
     float* band3 = band1 + (size_t)128 * 8;                                    // [i3][5]
-    float* bandN = band3 + (size_t)n3 * 5;                                     // [i4][5]
+    float* bandN = band3 + ring_pad4(n3 * 5);                                  // [i4][5]
     const float* __restrict__ P = st.P;
     float* __restrict__ Q = reinterpret_cast<float*>(a.Y);
     const bf16* __restrict__ M = reinterpret_cast<const bf16*>(a.M);
     const bool has1 = st.rband[0] != nullptr, has2 = st.rband[1] != nullptr;
     const bool has3 = st.rband[2] != nullptr, hasN = st.rband[3] != nullptr;
-    // this workgroup's plane and run of chunks (planes of one XCD side by side)
+    // this workgroup's plane and run of chunks: segment-major, so that an XCD
+    // holds a run of consecutive planes of one segment and most second-mode
+    // neighbours are read from its own L2
     const int L = (int)xcd_logical_block(blockIdx.x, gridDim.x);
-    const int p = L / rg.nseg, seg = L - p * rg.nseg;
+    const int seg = L / rg.nplane, p = L - seg * rg.nplane;
     const int cbeg = seg * rg.seg_len, cend = min(rg.cpp, cbeg + rg.seg_len);
     if (p >= rg.nplane || cbeg >= cend) return;   // uniform: the whole workgroup leaves
     const int tbase = p * rg.plane;

@@ -109,6 +109,7 @@ def test_unsupported_wide_regulariser():
                                  ((40, 24, 20, 16), (60, 36, 30, 24)),
                                  ((72, 32, 24, 16), (108, 48, 36, 24)),
                                  ((112, 16, 12, 8), (168, 24, 18, 12)),
+                                 ((112, 8, 6, 16), (168, 12, 9, 24)),   # 5 n_3 not a multiple of 4
                                  ((20, 100, 16, 8), (30, 150, 24, 12))])
 def test_tile_variants_match_oracle(n, m, chain):
     torch = torch_cuda()
