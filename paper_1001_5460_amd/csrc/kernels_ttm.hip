@@ -953,7 +953,9 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
             for (int h = 0; h < 2; ++h) {
                 rr[i][h] = *reinterpret_cast<const f4*>(R + off + 4 * h);
                 pp[i][h] = *reinterpret_cast<const f4*>(Pg + off + 4 * h);
-                if constexpr (!FR) xx[i][h] = *reinterpret_cast<const f4*>(Xsrc + off + 4 * h);
+                // x is next touched one iteration later: non-temporal, so that it
+                // does not push the vectors read soon (T, p, r) out of the caches
+                if constexpr (!FR) xx[i][h] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(Xsrc + off + 4 * h));
             }
         }
     };
@@ -1028,7 +1030,7 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
                     if constexpr (FR) {
                         *reinterpret_cast<f4*>(Rw + off + 4 * h) = nv[i][h];
                     } else {
-                        if (Xg) *reinterpret_cast<f4*>(Xg + off + 4 * h) = nx[i][h];
+                        if (Xg) __builtin_nontemporal_store(nx[i][h], reinterpret_cast<f4*>(Xg + off + 4 * h));
                         *reinterpret_cast<f4*>(Pg + off + 4 * h) = nv[i][h];
                     }
                 }
