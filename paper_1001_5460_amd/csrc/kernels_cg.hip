@@ -295,7 +295,9 @@ __global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __re
                       *reinterpret_cast<v4*>(x + i) = xv;
                   }
                   v4 rv = *reinterpret_cast<v4*>(r + i);
-                  const v4 qv = *reinterpret_cast<const v4*>(q + i);
+                  // q is dead after this read: non-temporal, so that the r just
+                  // written stays cached for the next pass, which reads it at once
+                  const v4 qv = __builtin_nontemporal_load(reinterpret_cast<const v4*>(q + i));
                   rv = rv - alpha * qv;
                   *reinterpret_cast<v4*>(r + i) = rv;
                   for (int u = 0; u < kItems; ++u) acc += (double)rv[u] * (double)rv[u];
