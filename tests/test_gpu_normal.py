@@ -110,6 +110,7 @@ def test_unsupported_wide_regulariser():
                                  ((72, 32, 24, 16), (108, 48, 36, 24)),
                                  ((112, 16, 12, 8), (168, 24, 18, 12)),
                                  ((112, 8, 6, 16), (168, 12, 9, 24)),   # 5 n_3 not a multiple of 4
+                                 ((112, 128, 12, 16), (168, 192, 18, 24)),  # plane sweeps of 3 tiles
                                  ((20, 100, 16, 8), (30, 150, 24, 12))])
 def test_tile_variants_match_oracle(n, m, chain):
     torch = torch_cuda()
