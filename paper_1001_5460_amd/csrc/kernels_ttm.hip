@@ -428,21 +428,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (threadIdx.x == 0) st.partials[blockIdx.x] = s;
 }
 
-// Variant 8 (normal_last_ring): one 1024-thread workgroup per CU.
-__global__ __launch_bounds__(RING_NT) __attribute__((amdgpu_waves_per_eu(4))) void k_normal_last_ring(
+// Variant 8 (normal_last_ring): one workgroup of NT threads per CU, gathers GD
+// tiles ahead, WPE waves per SIMD.
+template <int NT, int GD, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_normal_last_ring(
     StridedArgs a, StencilArgs<float> st, RingGeom rg, const int* done) {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[RING_NT / 64];
+    __shared__ double red[NT / 64];
     double dot = 0.0;
-    normal_last_ring(a, smem, st, rg, dot);
+    normal_last_ring<NT, GD>(a, smem, st, rg, dot);
     dot = wave_sum(dot);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int w = 0; w < RING_NT / 64; ++w) s += red[w];
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
         st.partials[blockIdx.x] = s;
     }
 }
@@ -469,10 +471,10 @@ static hipError_t go_last_ring(StridedArgs a, const StencilArgs<float>& st, int*
     rg.seg_len = (rg.cpp + rg.nseg - 1) / rg.nseg;
     int grid = n2 * rg.nseg;
     grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
-    hipError_t e = ensure_lds(k_normal_last_ring, lds);
+    hipError_t e = ensure_lds(k_normal_last_ring<RING_NT, 1, 4>, lds);
     if (e != hipSuccess) return e;
     *grid_out = grid;
-    k_normal_last_ring<<<grid, RING_NT, lds, s>>>(a, st, rg, done);
+    k_normal_last_ring<RING_NT, 1, 4><<<grid, RING_NT, lds, s>>>(a, st, rg, done);
     return hipGetLastError();
 }
 

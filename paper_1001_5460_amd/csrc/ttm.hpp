@@ -1166,9 +1166,13 @@ __host__ __device__ inline size_t ring_lds_bytes(int K, int n3, int nN) {
            (size_t)128 * 8 * 4 + (size_t)ring_pad4(n3 * 5) * 4 + (size_t)nN * 5 * 4;
 }
 
+// Registers of a tile's prefetched data: IPT rows' 4 of the 32 new ring
+// columns (rows tid / 8 + h NT / 8) and, for threads < 256, rows 2 kp and
+// 2 kp + 1 of the X tile, 8 columns.
+template <int IPT>
 struct RingRegs {
-    floatx4 p;   // 4 of the tile's 32 new ring columns, one row (row tid / 8)
-    bf16x8 x[2]; // rows 2 kp, 2 kp + 1 of the X tile, 8 columns (threads < 256)
+    floatx4 p[IPT];
+    bf16x8 x[2];
 };
 
 // Row of a thread's item: within each wave's block of 8 rows, lanes 8q .. 8q+7
@@ -1180,24 +1184,35 @@ __device__ __forceinline__ int ring_row(int tid) {
 
 // A tile starting at column T reads the ring window [T - 48, T + 80); going
 // from the tile at T - 32 to it, the new columns are [T + 48, T + 80), which
-// take the ring slots of [T - 80, T - 48).  ring_get loads a thread's 4 of
-// those 32 columns of one row (row tid / 8) and, for threads < 256, two rows
-// of the tile's X rows; rows past K and columns outside the tensor read a
-// clamped address and are stored as zero by ring_put.
-__device__ __forceinline__ void ring_get_cols(const float* __restrict__ P, int trail, int T, int K, floatx4& v) {
-    const int row = threadIdx.x >> 3, ch = threadIdx.x & 7;
+// take the ring slots of [T - 80, T - 48).  ring_get_cols loads a thread's 4
+// of those 32 columns of its rows (tid / 8 + h NT / 8); rows past K and
+// columns outside the tensor read a clamped address and are stored as zero by
+// ring_put_cols.
+template <int NT, int IPT>
+__device__ __forceinline__ void ring_get_cols(const float* __restrict__ P, int trail, int T, int K,
+                                              floatx4 (&v)[IPT]) {
+    const int ch = threadIdx.x & 7;
     const int t = T + 48 + 4 * ch;
-    const bool ok = row < K && t >= 0 && t < trail;
-    v = *reinterpret_cast<const floatx4*>(P + (int64_t)(ok ? row : 0) * trail + (ok ? t : 0));
+#pragma unroll
+    for (int h = 0; h < IPT; ++h) {
+        const int row = (threadIdx.x >> 3) + h * (NT / 8);
+        const bool ok = row < K && t >= 0 && t < trail;
+        v[h] = *reinterpret_cast<const floatx4*>(P + (int64_t)(ok ? row : 0) * trail + (ok ? t : 0));
+    }
 }
 
-__device__ __forceinline__ void ring_put_cols(const floatx4& v, float* ring, int trail, int T, int K) {
-    const int row = threadIdx.x >> 3, ch = threadIdx.x & 7;
+template <int NT, int IPT>
+__device__ __forceinline__ void ring_put_cols(const floatx4 (&v)[IPT], float* ring, int trail, int T, int K) {
+    const int ch = threadIdx.x & 7;
     const int t = T + 48 + 4 * ch;
-    if (row < K) {
-        floatx4 w = v;
-        if (t < 0 || t >= trail) w = floatx4{0.f, 0.f, 0.f, 0.f};
-        *reinterpret_cast<floatx4*>(ring + (row + 2) * RING_LD + (t & (RING_W - 1))) = w;
+#pragma unroll
+    for (int h = 0; h < IPT; ++h) {
+        const int row = (threadIdx.x >> 3) + h * (NT / 8);
+        if (row < K) {
+            floatx4 w = v[h];
+            if (t < 0 || t >= trail) w = floatx4{0.f, 0.f, 0.f, 0.f};
+            *reinterpret_cast<floatx4*>(ring + (row + 2) * RING_LD + (t & (RING_W - 1))) = w;
+        }
     }
 }
 
@@ -1227,12 +1242,18 @@ __device__ __forceinline__ void ring_put_x(const bf16x8 (&x)[2], bf16* Xs, int K
     }
 }
 
+// NT threads per workgroup, IPT = 1024 / NT items per thread (rows j and
+// j + NT / 8 of the same 4 columns, so the column's mode indices and band
+// rows are formed once), and the second mode's gathers issued GD tiles ahead.
+template <int NT, int GD>
 __device__ __forceinline__ void normal_last_ring(const StridedArgs& a, unsigned char* smem,
                                                  const StencilArgs<float>& st, const RingGeom& rg,
                                                  double& dot_acc) {
     typedef MT<bf16> T;
     typedef floatx4 vt;
     constexpr int E = 4, NKS = 4;
+    constexpr int IPT = 1024 / NT;
+    constexpr int RS = NT / 8;
     const int K = a.K;
     const int trail = (int)a.trail;
     const int nN = (int)st.ext[3], n3 = (int)st.ext[2], n2 = (int)st.ext[1];
@@ -1259,15 +1280,15 @@ __device__ __forceinline__ void normal_last_ring(const StridedArgs& a, unsigned 
     const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, l16 = lane & 15;
     // band rows and the ring's zero rows (-2, -1, K, K + 1)
     if (has1)
-        for (int u = tid; u < K * 8; u += RING_NT) {
+        for (int u = tid; u < K * 8; u += NT) {
             const int jj = u >> 3, d = u & 7;
             band1[u] = d < 5 ? st.rband[0][jj * 5 + d] : 0.f;
         }
     if (has3)
-        for (int u = tid; u < n3 * 5; u += RING_NT) band3[u] = st.rband[2][u];
+        for (int u = tid; u < n3 * 5; u += NT) band3[u] = st.rband[2][u];
     if (hasN)
-        for (int u = tid; u < nN * 5; u += RING_NT) bandN[u] = st.rband[3][u];
-    for (int u = tid; u < 4 * RING_LD; u += RING_NT) {
+        for (int u = tid; u < nN * 5; u += NT) bandN[u] = st.rband[3][u];
+    for (int u = tid; u < 4 * RING_LD; u += NT) {
         const int rr = u / RING_LD, cc = u - rr * RING_LD;
         const int row = rr < 2 ? rr : K + rr;   // ring rows 0, 1 and K + 2, K + 3
         ring[row * RING_LD + cc] = 0.f;
@@ -1285,90 +1306,116 @@ __device__ __forceinline__ void normal_last_ring(const StridedArgs& a, unsigned 
             off2[q] = (uint32_t)(dd * rg.plane) * 4u;
         }
     }
-    // this wave's G_1 fragments (16 output rows, all K) for the whole sweep
-    const int rt = wave >> 1, ct = wave & 1;
+    // this wave's 16 x 16 blocks (IPT of them, blocks wave IPT .. : rows 16 (b / 2),
+    // columns 16 (b % 2)) share their G_1 rows; the fragments stay in registers
+    const int blk0 = wave * IPT;
+    const int rt = blk0 >> 1;
     typename T::frag mreg[NKS];
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks)
         mreg[ks] = *reinterpret_cast<const typename T::frag*>(M + (int64_t)(rt * 16 + l16) * a.ldm +
                                                               ks * T::KSTEP + T::VEC * g);
-    // the item: row j, columns c .. c + 3 of every tile
-    const int j = ring_row(tid);
+    // the items: rows j[h], columns c .. c + 3 of every tile
     const int c = (tid & 7) * E;
-    const bool jok = j < K;
-    const int jc = jok ? j : K - 1;
-    const char* __restrict__ Pb = reinterpret_cast<const char*>(P);
-    auto gather = [&](int t0, vt (&gv)[4]) {
-        const uint32_t base = (uint32_t)(jc * trail + t0 + c) * 4u;
+    int jr[IPT], jc[IPT];
+    bool jok[IPT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) gv[q] = *reinterpret_cast<const vt*>(Pb + (base + off2[q]));
+    for (int h = 0; h < IPT; ++h) {
+        jr[h] = ring_row(tid) + h * RS;
+        jok[h] = jr[h] < K;
+        jc[h] = jok[h] ? jr[h] : K - 1;
+    }
+    const char* __restrict__ Pb = reinterpret_cast<const char*>(P);
+    auto gather = [&](int t0, vt (&gv)[IPT][4]) {
+#pragma unroll
+        for (int h = 0; h < IPT; ++h) {
+            const uint32_t base = (uint32_t)(jc[h] * trail + t0 + c) * 4u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) gv[h][q] = *reinterpret_cast<const vt*>(Pb + (base + off2[q]));
+        }
     };
     // prologue: the first tile's ring window [t0 - 48, t0 + 80) (the new
     // columns of the tiles at t0 - 96, t0 - 64, t0 - 32 and t0) and X tile,
-    // the second tile's data, the first tile's gathers
+    // the second tile's data, the first GD tiles' gathers
     const int t_first = tbase + cbeg * RING_TN;
     {
-        floatx4 w[4];
+        floatx4 w[4][IPT];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) ring_get_cols(P, trail, t_first - 96 + 32 * b, K, w[b]);
+        for (int b = 0; b < 4; ++b) ring_get_cols<NT, IPT>(P, trail, t_first - 96 + 32 * b, K, w[b]);
         bf16x8 x0[2];
         ring_get_x(a, t_first, K, x0);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) ring_put_cols(w[b], ring, trail, t_first - 96 + 32 * b, K);
+        for (int b = 0; b < 4; ++b) ring_put_cols<NT, IPT>(w[b], ring, trail, t_first - 96 + 32 * b, K);
         ring_put_x(x0, Xs, K);
     }
-    RingRegs rA, rB;   // the data of tile i + 1 is in rB before tile i for i - cbeg even, in rA for odd
-    vt gv[4];
-    gather(t_first, gv);
+    RingRegs<IPT> rA, rB;   // the data of tile i + 1 is in rB before tile i for i - cbeg even, in rA for odd
+    vt gA[IPT][4], gB[IPT][4];   // GD = 2: gathers of tile i in gA for i - cbeg even, in gB for odd
+    gather(t_first, gA);
+    if constexpr (GD == 2) gather(tbase + min(cbeg + 1, cend - 1) * RING_TN, gB);
     {
         const int t1 = tbase + min(cbeg + 1, cend - 1) * RING_TN;
-        ring_get_cols(P, trail, t1, K, rB.p);
+        ring_get_cols<NT, IPT>(P, trail, t1, K, rB.p);
         ring_get_x(a, t1, K, rB.x);
     }
     const float lam = (float)st.lam;
-    auto run_tile = [&](int ci, RingRegs& rnext, RingRegs& rfree) {
+    auto run_tile = [&](int ci, RingRegs<IPT>& rnext, RingRegs<IPT>& rfree, vt (&gv)[IPT][4]) {
         const int t0 = tbase + ci * RING_TN;
         __syncthreads();   // ring window, X tile and bands of this tile are in LDS
         const int t = t0 + c;
         const int col = t & (RING_W - 1);
-        const float* rrow = ring + (jc + 2) * RING_LD;
-        const vt pc = *reinterpret_cast<const vt*>(rrow + col);
-        // ---- middle modes, second then third (as every variant) ----
-        vt rmid = vt{0.f, 0.f, 0.f, 0.f};
-        if (has2) {
-            rmid += b2c[2] * pc;
-            rmid += b2c[0] * gv[0];
-            rmid += b2c[1] * gv[1];
-            rmid += b2c[3] * gv[2];
-            rmid += b2c[4] * gv[3];
+        const float* rrow[IPT];
+        vt pc[IPT], rmid[IPT];
+#pragma unroll
+        for (int h = 0; h < IPT; ++h) {
+            rrow[h] = ring + (jc[h] + 2) * RING_LD;
+            pc[h] = *reinterpret_cast<const vt*>(rrow[h] + col);
         }
-        // the next tile's gathers, then the data of the tile after it
-        const int tn = tbase + min(ci + 1, cend - 1) * RING_TN;
-        gather(tn, gv);
+        // ---- middle modes, second then third (as every variant) ----
+#pragma unroll
+        for (int h = 0; h < IPT; ++h) {
+            rmid[h] = vt{0.f, 0.f, 0.f, 0.f};
+            if (has2) {
+                rmid[h] += b2c[2] * pc[h];
+                rmid[h] += b2c[0] * gv[h][0];
+                rmid[h] += b2c[1] * gv[h][1];
+                rmid[h] += b2c[3] * gv[h][2];
+                rmid[h] += b2c[4] * gv[h][3];
+            }
+        }
+        // the gathers of the tile GD ahead, then the data of the tile after next
+        gather(tbase + min(ci + GD, cend - 1) * RING_TN, gv);
         {
             const int t2 = tbase + min(ci + 2, cend - 1) * RING_TN;
-            ring_get_cols(P, trail, t2, K, rfree.p);
+            ring_get_cols<NT, IPT>(P, trail, t2, K, rfree.p);
             ring_get_x(a, t2, K, rfree.x);
         }
         if (has3) {
             const int u = fast_div(t, st.smul[2], st.sshift[2]);
             const int i3 = u - fast_div(u, st.emul[2], st.eshift[2]) * n3;
             const float* br = band3 + i3 * 5;
-            vt nb[4];
+            int cq[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int d = q < 2 ? q - 2 : q - 1;
                 const int dd = (i3 + d >= 0 && i3 + d < n3) ? d : 0;
-                nb[q] = *reinterpret_cast<const vt*>(rrow + ((t + dd * nN) & (RING_W - 1)));
+                cq[q] = (t + dd * nN) & (RING_W - 1);
             }
-            rmid += br[2] * pc;
-            rmid += br[0] * nb[0];
-            rmid += br[1] * nb[1];
-            rmid += br[3] * nb[2];
-            rmid += br[4] * nb[3];
+#pragma unroll
+            for (int h = 0; h < IPT; ++h) {
+                vt nb[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) nb[q] = *reinterpret_cast<const vt*>(rrow[h] + cq[q]);
+                rmid[h] += br[2] * pc[h];
+                rmid[h] += br[0] * nb[0];
+                rmid[h] += br[1] * nb[1];
+                rmid[h] += br[3] * nb[2];
+                rmid[h] += br[4] * nb[3];
+            }
         }
-        // ---- MFMA: this wave's 16 x 16 block of the chain part ----
-        {
+        // ---- MFMA: this wave's 16 x 16 blocks of the chain part ----
+#pragma unroll
+        for (int b = 0; b < IPT; ++b) {
+            const int ct = (blk0 + b) & 1;
             typename T::acc acc = T::zero();
 #pragma unroll
             for (int ks = 0; ks < NKS; ++ks) {
@@ -1384,54 +1431,69 @@ __device__ __forceinline__ void normal_last_ring(const StridedArgs& a, unsigned 
         }
         __syncthreads();   // Q tile complete
         // ---- epilogue: modes 1 and N from the ring ----
-        if (jok) {
-            vt s = *reinterpret_cast<const vt*>(Qs + j * RING_LDQ + c);
-            vt reg = rmid;
+        vt reg[IPT];
+#pragma unroll
+        for (int h = 0; h < IPT; ++h) {
+            reg[h] = rmid[h];
             if (has1) {
-                const vt bl = *reinterpret_cast<const vt*>(band1 + j * 8);
-                const float b4 = band1[j * 8 + 4];
-                reg += bl[0] * *reinterpret_cast<const vt*>(rrow - 2 * RING_LD + col);
-                reg += bl[1] * *reinterpret_cast<const vt*>(rrow - RING_LD + col);
-                reg += bl[2] * pc;
-                reg += bl[3] * *reinterpret_cast<const vt*>(rrow + RING_LD + col);
-                reg += b4 * *reinterpret_cast<const vt*>(rrow + 2 * RING_LD + col);
+                const vt bl = *reinterpret_cast<const vt*>(band1 + jc[h] * 8);
+                const float b4 = band1[jc[h] * 8 + 4];
+                reg[h] += bl[0] * *reinterpret_cast<const vt*>(rrow[h] - 2 * RING_LD + col);
+                reg[h] += bl[1] * *reinterpret_cast<const vt*>(rrow[h] - RING_LD + col);
+                reg[h] += bl[2] * pc[h];
+                reg[h] += bl[3] * *reinterpret_cast<const vt*>(rrow[h] + RING_LD + col);
+                reg[h] += b4 * *reinterpret_cast<const vt*>(rrow[h] + 2 * RING_LD + col);
             }
-            if (hasN) {
-                float w[3 * E];
-                const vt pl = *reinterpret_cast<const vt*>(rrow + ((t - E) & (RING_W - 1)));
-                const vt pr = *reinterpret_cast<const vt*>(rrow + ((t + E) & (RING_W - 1)));
+        }
+        if (hasN) {
+            float w[IPT][3 * E];
+#pragma unroll
+            for (int h = 0; h < IPT; ++h) {
+                const vt pl = *reinterpret_cast<const vt*>(rrow[h] + ((t - E) & (RING_W - 1)));
+                const vt pr = *reinterpret_cast<const vt*>(rrow[h] + ((t + E) & (RING_W - 1)));
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    w[e] = pl[e];
-                    w[E + e] = pc[e];
-                    w[2 * E + e] = pr[e];
+                    w[h][e] = pl[e];
+                    w[h][E + e] = pc[h][e];
+                    w[h][2 * E + e] = pr[e];
                 }
-                const int i0 = t - fast_div(t, st.emul[3], st.eshift[3]) * nN;
+            }
+            const int i0 = t - fast_div(t, st.emul[3], st.eshift[3]) * nN;
 #pragma unroll
-                for (int q = 0; q < 5; ++q) {
-                    const vt v = *reinterpret_cast<const vt*>(bandN + i0 * 5 + 4 * q);
+            for (int q = 0; q < 5; ++q) {
+                const vt v = *reinterpret_cast<const vt*>(bandN + i0 * 5 + 4 * q);
+#pragma unroll
+                for (int h = 0; h < IPT; ++h)
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
                         const int x = 4 * q + m, e = x / 5, d = x - 5 * e - 2;
-                        reg[e] += v[m] * w[E + e + d];
+                        reg[h][e] += v[m] * w[h][E + e + d];
                     }
-                }
             }
-            const vt qv = s + lam * reg;
-            *reinterpret_cast<vt*>(Q + (int64_t)j * trail + t) = qv;
+        }
 #pragma unroll
-            for (int e = 0; e < E; ++e) dot_acc += (double)pc[e] * (double)qv[e];
+        for (int h = 0; h < IPT; ++h) {
+            if (jok[h]) {
+                const vt s = *reinterpret_cast<const vt*>(Qs + jr[h] * RING_LDQ + c);
+                const vt qv = s + lam * reg[h];
+                *reinterpret_cast<vt*>(Q + (int64_t)jr[h] * trail + t) = qv;
+#pragma unroll
+                for (int e = 0; e < E; ++e) dot_acc += (double)pc[h][e] * (double)qv[e];
+            }
         }
         __syncthreads();   // the ring's oldest 32 columns, the X and Q tiles are free
         if (ci + 1 < cend) {
-            ring_put_cols(rnext.p, ring, trail, tbase + (ci + 1) * RING_TN, K);
+            ring_put_cols<NT, IPT>(rnext.p, ring, trail, tbase + (ci + 1) * RING_TN, K);
             ring_put_x(rnext.x, Xs, K);
         }
     };
     for (int ci = cbeg; ci < cend; ci += 2) {
-        run_tile(ci, rB, rA);
+        run_tile(ci, rB, rA, gA);
         if (ci + 1 >= cend) break;
-        run_tile(ci + 1, rA, rB);
+        if constexpr (GD == 2)
+            run_tile(ci + 1, rA, rB, gB);
+        else
+            run_tile(ci + 1, rA, rB, gA);
     }
 }
 
