@@ -1133,18 +1133,19 @@ __device__ __forceinline__ void normal_last_pipe6(const StridedArgs& a, unsigned
 // ---------------------------------------------------------------------------
 // Variant 8 of the pipelined last pass (tensor order 4, BF16 chain, K = J <=
 // 128, n_N <= 24, n_N % 4 == 0, the plane of the second mode a multiple of 32
-// columns).  One workgroup of 1024 threads per CU sweeps a run of
-// consecutive 32-column tiles of one plane of the second mode; the
-// workgroups of one XCD hold neighbouring planes, so the second mode's
-// neighbour planes are read by neighbouring workgroups at nearly the same
-// time and come from that XCD's L2.  P stays in LDS as a ring of 128 columns
-// (the tile and 48 columns either side) that slides by 32 columns per tile:
-// the third mode's taps (columns +- n_N, +- 2 n_N), the last mode's and the
-// first mode's come from LDS; only the second mode's four planes are
-// gathered.  A tile's 32 new ring columns and its X rows are loaded into
-// registers two tiles ahead, its gathers one tile ahead, and issued in the
-// order they are waited for.  One item (4 columns of one row) per thread.
-// Every element's sums are those of the other variants, in the same order
+// columns).  One workgroup per CU sweeps a run of consecutive 32-column
+// tiles of one plane of the second mode; the workgroups of one XCD hold
+// neighbouring planes, so the second mode's neighbour planes are read by
+// neighbouring workgroups at nearly the same time and come from that XCD's
+// L2.  P stays in LDS as a ring of 128 columns (the tile and 48 columns
+// either side) that slides by 32 columns per tile: the third mode's taps
+// (columns +- n_N, +- 2 n_N), the last mode's and the first mode's come from
+// LDS; only the second mode's four planes are gathered.  A tile's 32 new ring
+// columns and its X rows are loaded into registers two tiles ahead, its
+// gathers GD tiles ahead, and issued in the order they are waited for.  An
+// item is 4 columns of one row; a workgroup of NT threads gives each thread
+// 1024 / NT of them (the launcher uses 1024 threads, one item each).  Every
+// element's sums are those of the other variants, in the same order
 // (identical Q).
 constexpr int RING_TN = 32;
 constexpr int RING_W = 128;          // ring columns (power of two)
