@@ -471,6 +471,7 @@ static hipError_t go_last_ring(StridedArgs a, const StencilArgs<float>& st, int*
     rg.seg_len = (rg.cpp + rg.nseg - 1) / rg.nseg;
     int grid = n2 * rg.nseg;
     grid = (grid + CTA_XCDS - 1) / CTA_XCDS * CTA_XCDS;
+    if (grid > kMaxGrid) return hipErrorNotSupported;   // one partial per workgroup
     hipError_t e = ensure_lds(k_normal_last_ring<RING_NT, 1, 4>, lds);
     if (e != hipSuccess) return e;
     *grid_out = grid;
