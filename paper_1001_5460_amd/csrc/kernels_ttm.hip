@@ -121,7 +121,9 @@ __device__ __forceinline__ void spipe_load(const StridedArgs& a, int64_t tile, b
             bf16x8 v;
 #pragma unroll
             for (int e = 0; e < 8; ++e) v[e] = (bf16)0.f;
-            if (k < a.K) v = *reinterpret_cast<const bf16x8*>(xb + (int64_t)k * a.trail + cg * 8);
+            // the input is dead after this pass: non-temporal, so that it leaves
+            // the caches before the vectors the next passes read
+            if (k < a.K) v = __builtin_nontemporal_load(reinterpret_cast<const bf16x8*>(xb + (int64_t)k * a.trail + cg * 8));
             r[2 * i + h] = v;
         }
     }

@@ -1224,7 +1224,8 @@ __device__ __forceinline__ void ring_get_x(const StridedArgs& a, int T, int K, b
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int k = min(2 * kp + h, K - 1);
-            x[h] = *reinterpret_cast<const bf16x8*>(X + (int64_t)k * a.trail + T + cg * 8);
+            // X is dead after this pass (non-temporal, as the middle pass's input)
+            x[h] = __builtin_nontemporal_load(reinterpret_cast<const bf16x8*>(X + (int64_t)k * a.trail + T + cg * 8));
         }
     }
 }
