@@ -294,9 +294,10 @@ __global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __re
                       xv = xv + alpha * pv;
                       *reinterpret_cast<v4*>(x + i) = xv;
                   }
-                  v4 rv = *reinterpret_cast<v4*>(r + i);
-                  // q is dead after this read: non-temporal, so that the r just
-                  // written stays cached for the next pass, which reads it at once
+                  // r's old value and q are dead after these reads: non-temporal, so
+                  // that the r just written stays cached for the next pass, which
+                  // reads it at once
+                  v4 rv = __builtin_nontemporal_load(reinterpret_cast<v4*>(r + i));
                   const v4 qv = __builtin_nontemporal_load(reinterpret_cast<const v4*>(q + i));
                   rv = rv - alpha * qv;
                   *reinterpret_cast<v4*>(r + i) = rv;

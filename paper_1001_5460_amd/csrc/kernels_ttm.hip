@@ -956,7 +956,11 @@ __global__ __launch_bounds__(CTA_WG) void k_tail_pipe(TailArgs a) {
             const int64_t off = (blk0 + bl) * bin + (int64_t)i1 * a.K2 + kc;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                rr[i][h] = *reinterpret_cast<const f4*>(R + off + 4 * h);
+                // the fused tail's r is next read by the update one iteration later:
+                // non-temporal, so that p, T and X stay cached for the passes in between
+                // (the preconditioner's form reads its r again at once and keeps it)
+                rr[i][h] = FR ? *reinterpret_cast<const f4*>(R + off + 4 * h)
+                              : __builtin_nontemporal_load(reinterpret_cast<const f4*>(R + off + 4 * h));
                 pp[i][h] = *reinterpret_cast<const f4*>(Pg + off + 4 * h);
                 // x is next touched one iteration later: non-temporal, so that it
                 // does not push the vectors read soon (T, p, r) out of the caches
