@@ -155,8 +155,10 @@ def test_cg_solve_from_a_given_start():
     assert oracle.relative_residual(host(X1), B, ref) <= 1.01e-10
     bad = 1e3 * dev(np.random.default_rng(6).standard_normal(n), torch.float64)
     X2, info2 = op.solve(Bd, bad.clone(), rtol=1e-10, max_iter=5000, x0_given=1, fallback_zero=1)
-    # the same solve from zero (the LDS sums' order may move an iteration)
-    assert info2["status"] == 0 and abs(info2["iters"] - info0["iters"]) <= 2
+    # the same solve from zero.  The LDS additions inside a tile run in no fixed
+    # order, so repeated zero-start solves differ in rounding: 190..193 iterations
+    # over 12 solves of this problem.  Keeping the start of 1e3 instead takes 247.
+    assert info2["status"] == 0 and abs(info2["iters"] - info0["iters"]) <= max(3, info0["iters"] // 20)
     assert oracle.relative_residual(host(X2), B, ref) <= 1.01e-10
 
 
