@@ -721,7 +721,9 @@ __global__ __launch_bounds__(CTA_WG) void k_last_nr_pipe(StridedArgs a, const fl
 #pragma unroll
             for (int y = 0; y < CT; ++y) {
                 const int j = min(jb + x * 16 + l16, a.J - 1);
-                rv[x][y] = *reinterpret_cast<const floatx4*>(R + (int64_t)j * a.trail + t0 + y * 16 + 4 * g);
+                // r is next read one iteration later: non-temporal
+                rv[x][y] = __builtin_nontemporal_load(
+                    reinterpret_cast<const floatx4*>(R + (int64_t)j * a.trail + t0 + y * 16 + 4 * g));
             }
         if (tile + step < a.ntiles) spipe_load(a, tile + step, r);
         typename T::acc acc[JT][CT];
