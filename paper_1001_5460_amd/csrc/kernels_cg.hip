@@ -294,13 +294,13 @@ __global__ __launch_bounds__(CTA_WG) void k_cg_update(T* __restrict__ x, T* __re
                       xv = xv + alpha * pv;
                       *reinterpret_cast<v4*>(x + i) = xv;
                   }
-                  // r's old value and q are dead after these reads: non-temporal, so
-                  // that the r just written stays cached for the next pass, which
-                  // reads it at once
+                  // r's old value and q are dead after these reads: non-temporal
                   v4 rv = __builtin_nontemporal_load(reinterpret_cast<v4*>(r + i));
                   const v4 qv = __builtin_nontemporal_load(reinterpret_cast<const v4*>(q + i));
                   rv = rv - alpha * qv;
-                  *reinterpret_cast<v4*>(r + i) = rv;
+                  // the new r streams out too: the next pass reads it non-temporally,
+                  // and kept out of the caches it leaves them to p, T and X
+                  __builtin_nontemporal_store(rv, reinterpret_cast<v4*>(r + i));
                   for (int u = 0; u < kItems; ++u) acc += (double)rv[u] * (double)rv[u];
               },
               {
