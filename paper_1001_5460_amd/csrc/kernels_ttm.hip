@@ -202,8 +202,9 @@ __global__ __launch_bounds__(CTA_WG) void k_strided_pipe(StridedArgs a, const in
         __syncthreads();
         for (int u = threadIdx.x; u < a.J * 8; u += CTA_WG) {
             const int j = u >> 3, c8 = (u & 7) * 8;
-            *reinterpret_cast<bf16x8*>(yb + (int64_t)j * a.trail + c8) =
-                *reinterpret_cast<const bf16x8*>(Ys + j * SPIPE_YLD + c8);
+            // the output is read once, by the next pass: non-temporal
+            __builtin_nontemporal_store(*reinterpret_cast<const bf16x8*>(Ys + j * SPIPE_YLD + c8),
+                                        reinterpret_cast<bf16x8*>(yb + (int64_t)j * a.trail + c8));
         }
         __syncthreads();  // Xs is rewritten by the next tile
     }
